@@ -1,0 +1,235 @@
+/*
+ * ladmm.h - batched ADMM for the Gamma Knife planning LP on one MI355X (gfx950).
+ *
+ * C ABI of the library.  The library solves, for k objective weightings at
+ * once, the LP
+ *
+ *     minimize c'x   subject to   A x <= b,   0 <= x <= u            (Eq. dual_problem)
+ *
+ * whose blocks are those of App. A: columns of A are the dose points (target
+ * surface TS, target interior TI, ring R, low-dose LD, organ at risk O) followed
+ * by 8 sector variables per isocentre; rows are 24 shot rows and one beam-on-time
+ * (BOT) row per isocentre.  The weights of each plan enter only b and u (Sec. 2.A
+ * and the end of Sec. 2.B).  The solver is the scaled-form ADMM of Eq. (admm)
+ * with the x-step of Eq. (partial_elimination) and the closed form after it,
+ * applied to all plans as matrix columns, with the row normalisation, BOT column
+ * scaling and per-plan step size rule of Sec. 3.C.
+ *
+ * Conventions that hold for every entry point:
+ *   - Return value: LADMM_OK (0) on success, LADMM_PENDING (>0) for a request
+ *     still running, a negative ladmm_status on error.  Not converging within
+ *     the iteration limit is NOT an error: it is a per-plan status.  After an
+ *     error, ladmm_last_error() returns a message for the calling thread.
+ *   - Pointers named host_* or documented as host memory are read during the
+ *     call only and copied; the caller keeps ownership.  Result buffers are
+ *     caller-owned host memory written by the library.  Handles are owned by
+ *     the library and released by the matching destroy call.
+ *   - Matrices are dense and row-major unless stated otherwise.
+ *   - Calls on one handle are not thread-safe unless stated; different cases
+ *     may be used from different threads.
+ */
+#ifndef LADMM_H
+#define LADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LADMM_OK = 0,
+  LADMM_PENDING = 1,
+  LADMM_E_INVALID = -1,   /* malformed argument or descriptor                */
+  LADMM_E_NOMEM = -2,     /* HBM budget of the context exceeded, or hipMalloc */
+  LADMM_E_DEVICE = -3,    /* a HIP runtime call failed                        */
+  LADMM_E_NUMERIC = -4,   /* Schur complement not positive definite, NaN/Inf  */
+  LADMM_E_STATE = -5,     /* unknown, destroyed or busy handle / ticket       */
+  LADMM_E_CANCELLED = -6
+} ladmm_status;
+
+/* Storage and arithmetic of the dose matrix and the dose-point iterates.  The
+ * Schur complement, its factor and inverse, and the small per-row iterates are
+ * always FP64. */
+typedef enum { LADMM_F64 = 0, LADMM_F32 = 1 } ladmm_precision;
+
+/* Dose-point group types (App. A subscripts TS, TI, R, LD, O). */
+typedef enum { LADMM_PT_TS = 0, LADMM_PT_TI = 1, LADMM_PT_RING = 2, LADMM_PT_LD = 3,
+               LADMM_PT_OAR = 4 } ladmm_point_type;
+
+typedef enum { LADMM_PLAN_CONVERGED = 0, LADMM_PLAN_MAX_ITER = 1, LADMM_PLAN_NUMERIC = 2,
+               LADMM_PLAN_RUNNING = 3 } ladmm_plan_status;
+
+/* One block of dose points (App. A, including its multi-target extension).
+ *   threshold : D_alpha in Gy (for an OAR, its max dose D_O); > 0.
+ *   share     : multiplies the plan weight of the group's type: q_k,A for a
+ *               target surface, q_k,V for a target interior, 1/n for a ring,
+ *               1 for low-dose and OAR groups.  >= 0. */
+typedef struct {
+  int32_t type;        /* ladmm_point_type */
+  int32_t structure;   /* target / LD level / OAR index (informational) */
+  double threshold;
+  double share;
+} ladmm_group;
+
+/* A planning case.  n_t = n_iso * n_sectors * n_collimators shot columns,
+ * ordered (i * n_sectors + s) * n_collimators + c (collimator fastest), which
+ * is the order of C = I (x) I_8 (x) 1_{1x3} in App. A. */
+typedef struct {
+  int32_t n_points;           /* N >= 1 dose points                              */
+  int32_t n_iso;              /* >= 1                                           */
+  int32_t n_sectors;          /* 8 on the Gamma Knife                           */
+  int32_t n_collimators;      /* 3 on the Gamma Knife                           */
+  const double *dose;         /* host, N x n_t dose rates phi >= 0, finite       */
+  const int32_t *point_group; /* host, N entries in [0, n_groups)                */
+  int32_t n_groups;
+  const ladmm_group *groups;  /* host, n_groups entries                          */
+  double prescription_mean;   /* D_T (mean target prescription), > 0             */
+  double phi_cal;             /* calibration dose rate, > 0                      */
+  int32_t precision;          /* ladmm_precision                                 */
+  int32_t row_normalize;      /* 1: unit 2-norm rows of A (Sec. 3.C)             */
+  double beta;                /* BOT column scale; <= 0 selects the rule         */
+  double beta_denominator;    /*   beta = (non-OAR points) / beta_denominator    */
+} ladmm_case_desc;
+
+/* Primal weights of one plan (Sec. 2.A): w_TS = w_TI = w_T. w_BOT > 0. */
+typedef struct { double w_t, w_r, w_ld, w_bot; } ladmm_weights;
+
+/* Solver options.  Step size per plan: rho_j = rho0 * sqrt(w0_bot / w_BOT,j)
+ * (Eq. rho_rule).  Plan j stops at the first check (every check_every
+ * iterations) where rel_gap <= tol_gap, r_pri <= tol_pri and r_dual <= tol_dual;
+ * tol_gap <= 0 runs exactly max_iter iterations (the fixed budget of Sec. 3.D). */
+typedef struct {
+  int32_t max_iter;
+  int32_t check_every;
+  double tol_gap, tol_pri, tol_dual;
+  double rho0, w0_bot;
+} ladmm_opts;
+
+/* Per-plan results; every pointer is caller-owned host memory or NULL.
+ *   t        : k x n_t shot times  t = E rho y2 (end of Sec. 2.B), >= 0
+ *   bot      : k x n_iso  tau_i = (phi_cal/D_T) max_s sum_c t_isc
+ *   objective: F_j(t), the planning objective (hinge terms + w_BOT sum tau)
+ *   dual_obj : c'z1, the dual-LP objective at the box-feasible copy
+ *   rel_gap  : |F + c'z1| / max(F, 1e-300)
+ *   r_pri    : ||x - z|| / max(||x||, ||z||);  r_dual: ||z - z_prev|| / ||y||
+ *   iters    : iterations run;  plan_status: ladmm_plan_status */
+typedef struct {
+  double *t, *bot, *objective, *dual_obj, *rel_gap, *r_pri, *r_dual;
+  int32_t *iters, *plan_status;
+} ladmm_result;
+
+typedef struct ladmm_ctx ladmm_ctx;
+typedef struct ladmm_case ladmm_case;
+typedef struct ladmm_batch ladmm_batch;
+
+/* Context on one device.  hbm_budget_bytes = 0 means no budget.  Every case
+ * and batch allocation is charged to the budget; a request that would exceed it
+ * fails with LADMM_E_NOMEM before touching the device. */
+int ladmm_ctx_create(int device, size_t hbm_budget_bytes, ladmm_ctx **out);
+/* Destroying a context (or a case) that still has live cases (or batches) is
+ * allowed: the object is freed when its last dependant is destroyed. */
+int ladmm_ctx_destroy(ladmm_ctx *ctx);
+/* Bytes currently charged to the context. */
+size_t ladmm_ctx_used_bytes(const ladmm_ctx *ctx);
+
+/* Case setup (Sec. 2.B, 3.C): copies the dose matrix to HBM; computes the row
+ * scales E, beta, the Schur complement S = A A' + I (FP64), its Cholesky factor
+ * and S^-1 = L^-T L^-1 (FP64); stores the scaled dose block in the requested
+ * precision.  LADMM_E_INVALID for negative or non-finite doses, bad group
+ * indices, non-positive thresholds; LADMM_E_NUMERIC if S is not SPD. */
+int ladmm_create_case(ladmm_ctx *ctx, const ladmm_case_desc *desc, ladmm_case **out);
+int ladmm_destroy_case(ladmm_case *c);
+/* Row scales E (m_A = n_t + n_iso values) and beta of a case, to host memory. */
+int ladmm_case_scaling(const ladmm_case *c, double *E, double *beta);
+/* Inspection of the cached setup, for verification: the Schur complement
+ * S = A_s A_s' + I of the scaled LP (Eq. partial_elimination) and its inverse,
+ * each m_A x m_A FP64 host memory (rows: shot rows, then BOT rows).  Either
+ * pointer may be NULL. */
+int ladmm_case_schur(const ladmm_case *c, double *S, double *S_inv);
+/* Setup timing in milliseconds (device time of the setup kernels). */
+double ladmm_case_setup_ms(const ladmm_case *c);
+
+/* A batch of k plans on a case, holding the iterates in HBM.
+ *   ld_mask: NULL, or host k x ceil(N/64) uint64 words; bit (p % 64) of word
+ *            p / 64 of row j set means dose point p is in plan j's low-dose
+ *            set p_j (Sec. 2.C.2).  Low-dose points outside p_j get u = 0 and
+ *            the LD weight of plan j is spread over |p_j| points.  Bits of
+ *            non-LD points are ignored.
+ *   rho:     NULL (rule of Eq. rho_rule from opts) or host k values > 0.
+ * Iterates start at zero. */
+int ladmm_batch_create(ladmm_case *c, int32_t k, const ladmm_weights *w,
+                       const uint64_t *ld_mask, const double *rho,
+                       const ladmm_opts *opts, ladmm_batch **out);
+int ladmm_batch_destroy(ladmm_batch *b);
+/* Exactly `iters` ADMM iterations on every active plan, no convergence checks. */
+int ladmm_batch_iterate(ladmm_batch *b, int32_t iters);
+/* Iterate with checks until every plan has stopped or max_iter is reached. */
+int ladmm_batch_run(ladmm_batch *b);
+/* Evaluate the per-plan statistics at the current iterate and fill `out`. */
+int ladmm_batch_results(ladmm_batch *b, ladmm_result *out);
+/* Iterates in the oracle's variables (scaled LP of Sec. 3.C), host FP64,
+ * row-major with one column per plan: z1, y1 are n_A x k (points then
+ * sectors), z2, y2 are m_A x k (shot rows then BOT rows).  Any pointer may be
+ * NULL.  Import requires z1 = clip(z1 + y1, 0, u) and z2 = min(z2 + y2, b),
+ * which every ADMM iterate satisfies; the device keeps q = z + y only. */
+int ladmm_batch_export(ladmm_batch *b, double *z1, double *y1, double *z2, double *y2);
+int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1,
+                       const double *z2, const double *y2);
+/* Device time of the iterations run so far, in milliseconds, and the number of
+ * plan-iterations. */
+int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_iterations);
+
+/* Per-kernel timing.  With profiling on, every kernel launch of an iteration
+ * is bracketed by HIP events recorded on the batch's stream; the elapsed times
+ * are accumulated per kernel class when each run chunk completes.  Classes:
+ * 0 GEMM1 (A_s W, the dose-point part of the right-hand side), 1 rhs assembly,
+ * 2 S^-1 product, 3 post (small-side update), 4 GEMM2 (closed-form x-step with
+ * the fused z- and y-steps), 5 objective product, 6 shot-time scaling,
+ * 7 finalize.  ms_total and launches are arrays of LADMM_N_KERNEL_CLASSES. */
+#define LADMM_N_KERNEL_CLASSES 8
+int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
+int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
+
+/* One call: create a batch, run it to convergence, write results, destroy it. */
+int ladmm_solve_batch(ladmm_case *c, int32_t k, const ladmm_weights *w,
+                      const uint64_t *ld_mask, const ladmm_opts *opts, ladmm_result *out);
+
+/* Low-dose band of Sec. 2.C.1 from the current shot times of a batch: bit v of
+ * row j of vol_bits is set iff D_LD <= d_j(v) < D_LD + delta, where
+ * d_j = phi_vox t_j is the dose of plan j at candidate voxel v (FP64 product).
+ *   phi_vox : host, n_vox x n_t dose rates of the candidate voxels, >= 0.
+ *   vol_bits: host output, k x ceil(n_vox/64) words (bit v % 64 of word v/64). */
+int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double d_ld,
+                        double delta, uint64_t *vol_bits);
+
+/* Algorithm 1 (overlapping low-dose point sampling, Sec. 2.C.2), integer exact.
+ * Plans are taken in order of decreasing density w_j = min(1, N_LD,j / |V_j|)
+ * (ties: lower index first); a plan with |V_j| = 0 or N_LD,j <= 0 gets no
+ * points.  Point counts are round-half-even((N_LD,j / |V_j|) * |X|) in IEEE
+ * double, clamped to |X|.  "Randomly select K of X" takes the K members of X
+ * with the smallest (h, v), h = sm(sm(sm(seed) ^ step) ^ v), sm the SplitMix64
+ * output function, step = 2 r (thinning of the running union) and 2 r + 1
+ * (new region) for the plan at rank r.
+ *   vol_bits: host, k x ceil(n_vox/64) words, the volumes V_j.
+ *   n_ld    : host, k desired point counts N_LD,j.
+ *   P       : host output, capacity n_vox; the sorted voxel indices of the union.
+ *   nP      : host output, |P|.
+ *   masks   : host output, k rows of ceil(n_vox/64) words; bit i % 64 of word
+ *             i / 64 of row j is set iff P[i] is in p_j (words past
+ *             ceil(|P|/64) are zero).
+ * Runs on the context's device; allocates its scratch for the call. */
+int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint64_t *vol_bits,
+                           const int32_t *n_ld, uint64_t seed, int64_t *P, int64_t *nP,
+                           uint64_t *masks);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char *ladmm_last_error(void);
+/* Library version string. */
+const char *ladmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LADMM_H */

@@ -1,0 +1,1209 @@
+// C ABI of the batched ADMM library: contexts, resident cases, plan batches.
+//
+// The host code here validates descriptors, owns device memory, and orders
+// the kernel launches of one ADMM iteration (Sec. 2.B) on the batch's stream:
+//
+//   GEMM1   P1 = D^' W,   W = z1 - y1 of the dose points     (A_s x1 part of
+//           Eq. partial_elimination; split over point chunks)
+//   rhs     r = A_s (z1 - y1 - c/rho) - (z2 - y2)
+//   solve   v = S^-1 r                                      (cached FP64 inverse)
+//   post    x2/z2/y2 update and the sector variables
+//   GEMM2   q <- clip(q, 0, u) - c/rho - D^ v  for the dose points (closed form
+//           of the x-step with the z- and y-steps of Eq. (admm) fused)
+//
+// and, every check_every iterations, the planning objective F(t) of the
+// current shot times with the stopping statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ladmm.h"
+#include "kernels.h"
+
+using namespace ladmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPC(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(LADMM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct ladmm_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  int refs = 0;              // live cases
+  bool destroyed = false;    // destroy requested while cases were alive
+  std::mutex mu;
+};
+
+namespace {
+
+// Device allocation charged to a context's HBM budget.
+int ctx_alloc(ladmm_ctx *ctx, void **p, size_t bytes, size_t *charged) {
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+      return fail(LADMM_E_NOMEM, "HBM budget exceeded: need " + std::to_string(bytes) +
+                                     " more bytes, " + std::to_string(ctx->budget - ctx->used) +
+                                     " left");
+    ctx->used += bytes;
+  }
+  hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->used -= bytes;
+    *p = nullptr;
+    return fail(LADMM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  *charged += bytes;
+  return LADMM_OK;
+}
+
+void ctx_release(ladmm_ctx *ctx, size_t bytes) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->used -= std::min(bytes, ctx->used);
+}
+
+void ctx_ref(ladmm_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->refs++;
+}
+
+// Drop a case's reference; frees a context whose destroy call came first.
+void ctx_unref(ladmm_ctx *ctx) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->refs--;
+    last = ctx->destroyed && ctx->refs == 0;
+  }
+  if (last) delete ctx;
+}
+
+}  // namespace
+
+struct ladmm_case {
+  ladmm_ctx *ctx = nullptr;
+  int precision = LADMM_F64;
+  int N = 0, Np = 0, n_iso = 0, S = 8, C = 3, n_t = 0, ntp = 0, n_sec = 0, mAp = 0, G = 0;
+  double beta = 1.0, cs = 0.0;
+  int row_normalize = 1;
+  SmallLayout L{};
+  void *D = nullptr;         // Np x ntp, scaled point block of A' (precision T)
+  void *sig = nullptr;       // Np (T)
+  int32_t *grp = nullptr;    // Np
+  int32_t *is_ld = nullptr;  // G + 1
+  int32_t *is_oar = nullptr; // G + 1
+  double *E = nullptr;       // mAp
+  double *gvec = nullptr;    // ntp
+  double *Smat = nullptr;    // mAp x mAp
+  double *Sinv = nullptr;    // mAp x mAp
+  std::vector<ladmm_group> groups;
+  std::vector<int32_t> hgrp;
+  std::vector<int64_t> counts;
+  std::vector<double> hE;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  float setup_ms = 0.f;
+  int nchunk1 = 1, nchunk2 = 1;
+  int refs = 0;              // live batches
+  bool destroyed = false;    // destroy requested while batches were alive
+};
+
+struct ladmm_batch {
+  ladmm_case *c = nullptr;
+  int k = 0, kp = 0, mask_words = 0;
+  hipStream_t stream = nullptr;
+  void *q = nullptr;          // Np x kp (T)
+  double *qs = nullptr;       // n_sec x kp
+  double *q2 = nullptr;       // mAp x kp
+  void *utab = nullptr;       // (G + 1) x kp (T)
+  uint64_t *mask = nullptr;   // kp x mask_words
+  double *invrho = nullptr, *bbot = nullptr, *wbot = nullptr;
+  int32_t *active = nullptr;
+  void *P1 = nullptr;
+  double *r = nullptr, *P2 = nullptr;
+  void *vT = nullptr, *that = nullptr;
+  double *admm_stats = nullptr, *post_stats = nullptr, *obj_stats = nullptr, *fin = nullptr;
+  int admm_blocks = 0, post_blocks = 0, obj_blocks = 0;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  std::vector<ladmm_weights> w;
+  std::vector<double> rho;
+  std::vector<int32_t> h_active, status, iters;
+  std::vector<double> rec;    // k x kFinal, per-plan statistics at the last check
+  double *h_fin = nullptr;    // pinned kp x kFinal
+  ladmm_opts opts{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double iterate_ms = 0.0;
+  int64_t plan_iters = 0;
+  int iters_run = 0;
+  // per-kernel event timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;      // kind of each recorded pair
+  size_t ev_used = 0;            // events handed out in the current chunk
+  double kms[LADMM_N_KERNEL_CLASSES] = {};
+  int64_t kcount[LADMM_N_KERNEL_CLASSES] = {};
+};
+
+namespace {
+
+int case_alloc(ladmm_case *c, void **p, size_t bytes) {
+  int rc = ctx_alloc(c->ctx, p, bytes, &c->bytes);
+  if (rc == LADMM_OK) c->allocs.push_back(*p);
+  return rc;
+}
+
+int batch_alloc(ladmm_batch *b, void **p, size_t bytes) {
+  int rc = ctx_alloc(b->c->ctx, p, bytes, &b->bytes);
+  if (rc == LADMM_OK) b->allocs.push_back(*p);
+  return rc;
+}
+
+template <typename T>
+PointTable<T> point_table(const ladmm_batch *b) {
+  const ladmm_case *c = b->c;
+  PointTable<T> pt;
+  pt.grp = c->grp;
+  pt.sig = (const T *)c->sig;
+  pt.is_ld = c->is_ld;
+  pt.is_oar = c->is_oar;
+  pt.utab = (const T *)b->utab;
+  pt.ldu = b->kp;
+  pt.mask = b->mask;
+  pt.mask_words = b->mask_words;
+  return pt;
+}
+
+SmallArgs small_args(const ladmm_batch *b) {
+  const ladmm_case *c = b->c;
+  SmallArgs a;
+  a.L = c->L;
+  a.E = c->E;
+  a.gvec = c->gvec;
+  a.beta = c->beta;
+  a.cs = c->cs;
+  a.invrho = b->invrho;
+  a.bbot = b->bbot;
+  a.active = b->active;
+  a.kp = b->kp;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// case setup
+// ---------------------------------------------------------------------------
+template <typename T>
+int setup_precision(ladmm_case *c, const double *Dt, hipStream_t s) {
+  void *p = nullptr;
+  int rc = case_alloc(c, &p, (size_t)c->Np * c->ntp * sizeof(T));
+  if (rc) return rc;
+  c->D = p;
+  HIPC(scale_columns<T>(s, Dt, c->E, (T *)c->D, c->Np, c->ntp));
+  return LADMM_OK;
+}
+
+int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out) {
+  if (!ctx || !d || !out) return fail(LADMM_E_INVALID, "null argument");
+  if (d->n_points < 1 || d->n_iso < 1 || d->n_sectors < 1 || d->n_collimators < 1)
+    return fail(LADMM_E_INVALID, "sizes must be positive");
+  if (!d->dose || !d->point_group || !d->groups || d->n_groups < 1)
+    return fail(LADMM_E_INVALID, "dose, point_group and groups are required");
+  if (!(d->prescription_mean > 0) || !(d->phi_cal > 0))
+    return fail(LADMM_E_INVALID, "prescription_mean and phi_cal must be > 0");
+  if (d->precision != LADMM_F64 && d->precision != LADMM_F32)
+    return fail(LADMM_E_INVALID, "unknown precision");
+  const int n_t = d->n_iso * d->n_sectors * d->n_collimators;
+  for (int g = 0; g < d->n_groups; ++g) {
+    const ladmm_group &gr = d->groups[g];
+    if (gr.type < LADMM_PT_TS || gr.type > LADMM_PT_OAR)
+      return fail(LADMM_E_INVALID, "group " + std::to_string(g) + ": bad type");
+    if (!(gr.threshold > 0) || !std::isfinite(gr.threshold))
+      return fail(LADMM_E_INVALID, "group " + std::to_string(g) + ": threshold must be > 0");
+    if (!(gr.share >= 0) || !std::isfinite(gr.share))
+      return fail(LADMM_E_INVALID, "group " + std::to_string(g) + ": share must be >= 0");
+  }
+  std::vector<int64_t> counts(d->n_groups, 0);
+  for (int p = 0; p < d->n_points; ++p) {
+    const int g = d->point_group[p];
+    if (g < 0 || g >= d->n_groups)
+      return fail(LADMM_E_INVALID, "point " + std::to_string(p) + ": group out of range");
+    counts[g]++;
+  }
+  const size_t nd = (size_t)d->n_points * n_t;
+  for (size_t e = 0; e < nd; ++e) {
+    const double v = d->dose[e];
+    if (!(v >= 0.0) || !std::isfinite(v))
+      return fail(LADMM_E_INVALID, "dose entry " + std::to_string(e) + " is negative or not finite");
+  }
+
+  ladmm_case *c = new ladmm_case();
+  c->ctx = ctx;
+  c->precision = d->precision;
+  c->N = d->n_points;
+  c->Np = round_up(c->N, kTileRows);
+  c->n_iso = d->n_iso;
+  c->S = d->n_sectors;
+  c->C = d->n_collimators;
+  c->n_t = n_t;
+  c->ntp = round_up(n_t, kSmallAlign);
+  c->n_sec = d->n_iso * d->n_sectors;
+  c->mAp = round_up(c->ntp + c->n_iso, kSmallAlign);
+  c->G = d->n_groups;
+  c->cs = d->phi_cal / d->prescription_mean;
+  c->row_normalize = d->row_normalize ? 1 : 0;
+  c->groups.assign(d->groups, d->groups + d->n_groups);
+  c->hgrp.assign(d->point_group, d->point_group + d->n_points);
+  c->counts = counts;
+  if (d->beta > 0) {
+    c->beta = d->beta;
+  } else {
+    const double den = d->beta_denominator > 0 ? d->beta_denominator : 2000.0;
+    int64_t non_oar = 0;
+    for (int g = 0; g < d->n_groups; ++g)
+      if (d->groups[g].type != LADMM_PT_OAR) non_oar += counts[g];
+    c->beta = (double)non_oar / den;
+    if (!(c->beta > 0)) c->beta = 1.0;
+  }
+  c->L = SmallLayout{c->n_t, c->ntp, c->n_iso, c->mAp, c->n_sec, c->S, c->C};
+  // GEMM split factors depend on the case only, so a plan's arithmetic does
+  // not depend on how many other plans share its batch.
+  c->nchunk1 = std::max(1, std::min((1024 + c->ntp / 64 - 1) / (c->ntp / 64), c->Np / 256));
+  c->nchunk2 = std::max(1, std::min((512 + c->mAp / 64 - 1) / (c->mAp / 64), c->mAp / 64));
+
+  auto cleanup = [&](int rc) {
+    for (void *p : c->allocs) hipFree(p);
+    ctx_release(ctx, c->bytes);
+    delete c;
+    return rc;
+  };
+  int rc;
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s;
+  HIPC(hipStreamCreate(&s));
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  HIPC(hipEventRecord(e0, s));
+
+  // point tables
+  std::vector<double> hsig(c->Np, 0.0), hinv(c->Np, 0.0);
+  std::vector<int32_t> hgrp(c->Np, c->G);
+  for (int p = 0; p < c->N; ++p) {
+    const ladmm_group &gr = d->groups[d->point_group[p]];
+    hsig[p] = (gr.type == LADMM_PT_TS || gr.type == LADMM_PT_TI) ? 1.0 : -1.0;
+    hinv[p] = 1.0 / gr.threshold;
+    hgrp[p] = d->point_group[p];
+  }
+  std::vector<int32_t> hld(c->G + 1, 0), hoar(c->G + 1, 0);
+  for (int g = 0; g < c->G; ++g) {
+    hld[g] = d->groups[g].type == LADMM_PT_LD;
+    hoar[g] = d->groups[g].type == LADMM_PT_OAR;
+  }
+  void *p = nullptr;
+  double *dphi = nullptr, *dsig64 = nullptr, *dinv = nullptr, *Dt = nullptr, *K = nullptr;
+  double *Pk = nullptr, *Sw = nullptr, *X = nullptr, *Pg = nullptr, *sigmat = nullptr;
+  int *dinfo = nullptr;
+  std::vector<void *> temps;
+  auto talloc = [&](void **pp, size_t bytes) -> int {
+    hipError_t e = hipMalloc(pp, bytes ? bytes : 1);
+    if (e != hipSuccess) return fail(LADMM_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    temps.push_back(*pp);
+    return LADMM_OK;
+  };
+  auto tclean = [&](int code) {
+    hipStreamSynchronize(s);
+    for (void *t : temps) hipFree(t);
+    hipStreamDestroy(s);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return cleanup(code);
+  };
+#define SETUP_HIP(call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      fail(LADMM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));               \
+      return tclean(LADMM_E_DEVICE);                                                         \
+    }                                                                                        \
+  } while (0)
+#define SETUP_RC(expr)            \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_) return tclean(rc_);  \
+  } while (0)
+
+  const size_t Tsz = c->precision == LADMM_F64 ? sizeof(double) : sizeof(float);
+  SETUP_RC(case_alloc(c, &p, (size_t)c->Np * sizeof(int32_t)));
+  c->grp = (int32_t *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)c->Np * Tsz));
+  c->sig = p;
+  SETUP_RC(case_alloc(c, &p, (size_t)(c->G + 1) * sizeof(int32_t)));
+  c->is_ld = (int32_t *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)(c->G + 1) * sizeof(int32_t)));
+  c->is_oar = (int32_t *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)c->mAp * sizeof(double)));
+  c->E = (double *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)c->ntp * sizeof(double)));
+  c->gvec = (double *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)c->mAp * c->mAp * sizeof(double)));
+  c->Smat = (double *)p;
+  SETUP_RC(case_alloc(c, &p, (size_t)c->mAp * c->mAp * sizeof(double)));
+  c->Sinv = (double *)p;
+
+  SETUP_HIP(hipMemcpyAsync(c->grp, hgrp.data(), c->Np * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SETUP_HIP(hipMemcpyAsync(c->is_ld, hld.data(), (c->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SETUP_HIP(hipMemcpyAsync(c->is_oar, hoar.data(), (c->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (c->precision == LADMM_F64) {
+    SETUP_HIP(hipMemcpyAsync(c->sig, hsig.data(), c->Np * sizeof(double), hipMemcpyHostToDevice, s));
+  } else {
+    std::vector<float> fs(hsig.begin(), hsig.end());
+    SETUP_HIP(hipMemcpyAsync(c->sig, fs.data(), c->Np * sizeof(float), hipMemcpyHostToDevice, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+  }
+
+  // dose matrix -> D~ = sign * phi / D_alpha (FP64, padded)
+  SETUP_RC(talloc((void **)&dphi, nd * sizeof(double)));
+  SETUP_RC(talloc((void **)&dsig64, c->Np * sizeof(double)));
+  SETUP_RC(talloc((void **)&dinv, c->Np * sizeof(double)));
+  SETUP_RC(talloc((void **)&Dt, (size_t)c->Np * c->ntp * sizeof(double)));
+  SETUP_HIP(hipMemcpyAsync(dphi, d->dose, nd * sizeof(double), hipMemcpyHostToDevice, s));
+  SETUP_HIP(hipMemcpyAsync(dsig64, hsig.data(), c->Np * sizeof(double), hipMemcpyHostToDevice, s));
+  SETUP_HIP(hipMemcpyAsync(dinv, hinv.data(), c->Np * sizeof(double), hipMemcpyHostToDevice, s));
+  SETUP_HIP(scale_dose(s, dphi, c->N, n_t, dsig64, dinv, Dt, c->Np, c->ntp));
+
+  // K = D~' D~ (FP64 SYRK through the split-K product), then E and S
+  const int nck = std::max(1, std::min(64, c->Np / 256));
+  SETUP_RC(talloc((void **)&Pk, (size_t)nck * c->ntp * c->ntp * sizeof(double)));
+  SETUP_RC(talloc((void **)&K, (size_t)c->ntp * c->ntp * sizeof(double)));
+  SETUP_HIP(gemm_tn<double>(s, Dt, c->ntp, Dt, c->ntp, Pk, c->ntp, c->ntp, c->ntp, c->Np, nck, nullptr));
+  SETUP_HIP(reduce_partials<double>(s, Pk, (size_t)c->ntp * c->ntp, nck, c->ntp, c->ntp, c->ntp, K, c->ntp));
+  SETUP_HIP(assemble_schur(s, K, c->ntp, c->L, c->cs, c->beta, 0.0, c->row_normalize, c->E, c->Smat));
+
+  // g = A_s (-c) on the shot rows: E_t sum_p sign_p D~[p][t]
+  SETUP_RC(talloc((void **)&sigmat, (size_t)c->Np * 32 * sizeof(double)));
+  {
+    std::vector<double> hs(c->Np * 32, 0.0);
+    for (int q = 0; q < c->Np; ++q) hs[(size_t)q * 32] = hsig[q];
+    SETUP_HIP(hipMemcpyAsync(sigmat, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    SETUP_RC(talloc((void **)&Pg, (size_t)nck * c->ntp * 32 * sizeof(double)));
+    SETUP_HIP(gemm_tn<double>(s, Dt, c->ntp, sigmat, 32, Pg, 32, c->ntp, 32, c->Np, nck, nullptr));
+    double *gt = nullptr;
+    SETUP_RC(talloc((void **)&gt, (size_t)c->ntp * 32 * sizeof(double)));
+    SETUP_HIP(reduce_partials<double>(s, Pg, (size_t)c->ntp * 32, nck, c->ntp, 32, 32, gt, 32));
+    std::vector<double> hgt((size_t)c->ntp * 32), hE(c->mAp);
+    SETUP_HIP(hipMemcpyAsync(hgt.data(), gt, hgt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipMemcpyAsync(hE.data(), c->E, c->mAp * sizeof(double), hipMemcpyDeviceToHost, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    std::vector<double> hg(c->ntp, 0.0);
+    for (int t = 0; t < c->n_t; ++t) hg[t] = hE[t] * hgt[(size_t)t * 32];
+    SETUP_HIP(hipMemcpyAsync(c->gvec, hg.data(), c->ntp * sizeof(double), hipMemcpyHostToDevice, s));
+    SETUP_HIP(hipStreamSynchronize(s));
+    c->hE = hE;
+  }
+
+  // Cholesky of S (FP64), then S^-1 = X' X with X = L^-1
+  SETUP_RC(talloc((void **)&Sw, (size_t)c->mAp * c->mAp * sizeof(double)));
+  SETUP_RC(talloc((void **)&X, (size_t)c->mAp * c->mAp * sizeof(double)));
+  SETUP_RC(talloc((void **)&dinfo, sizeof(int)));
+  SETUP_HIP(hipMemsetAsync(dinfo, 0, sizeof(int), s));
+  SETUP_HIP(hipMemcpyAsync(Sw, c->Smat, (size_t)c->mAp * c->mAp * sizeof(double), hipMemcpyDeviceToDevice, s));
+  SETUP_HIP(cholesky(s, Sw, c->mAp, c->mAp, dinfo));
+  SETUP_HIP(tri_inverse(s, Sw, X, c->mAp, c->mAp));
+  {
+    const int nci = std::max(1, std::min(16, c->mAp / 64));
+    double *Pi = nullptr;
+    SETUP_RC(talloc((void **)&Pi, (size_t)nci * c->mAp * c->mAp * sizeof(double)));
+    SETUP_HIP(gemm_tn<double>(s, X, c->mAp, X, c->mAp, Pi, c->mAp, c->mAp, c->mAp, c->mAp, nci, nullptr));
+    SETUP_HIP(reduce_partials<double>(s, Pi, (size_t)c->mAp * c->mAp, nci, c->mAp, c->mAp, c->mAp, c->Sinv, c->mAp));
+  }
+  int hinfo = 0;
+  SETUP_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+
+  // scaled dose block in the iteration precision: D^ = D~ diag(E)
+  if (c->precision == LADMM_F64) {
+    SETUP_RC(setup_precision<double>(c, Dt, s));
+  } else {
+    SETUP_RC(setup_precision<float>(c, Dt, s));
+  }
+  SETUP_HIP(hipEventRecord(e1, s));
+  SETUP_HIP(hipStreamSynchronize(s));
+  if (hinfo != 0) {
+    fail(LADMM_E_NUMERIC, "Schur complement is not positive definite");
+    return tclean(LADMM_E_NUMERIC);
+  }
+  SETUP_HIP(hipEventElapsedTime(&c->setup_ms, e0, e1));
+  for (void *t : temps) hipFree(t);
+  hipStreamDestroy(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+#undef SETUP_HIP
+#undef SETUP_RC
+  (void)rc;
+  ctx_ref(ctx);
+  *out = c;
+  return LADMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+void case_free(ladmm_case *c) {
+  hipSetDevice(c->ctx->device);
+  for (void *p : c->allocs) hipFree(p);
+  ctx_release(c->ctx, c->bytes);
+  ladmm_ctx *ctx = c->ctx;
+  delete c;
+  ctx_unref(ctx);
+}
+
+// Drop a batch's reference; frees a case whose destroy call came first.
+void case_unref(ladmm_case *c) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> lk(c->ctx->mu);
+    c->refs--;
+    last = c->destroyed && c->refs == 0;
+  }
+  if (last) case_free(c);
+}
+
+int destroy_batch_impl(ladmm_batch *b) {
+  if (!b) return LADMM_OK;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  for (hipEvent_t e : b->ev_pool) hipEventDestroy(e);
+  for (void *p : b->allocs) hipFree(p);
+  ctx_release(b->c->ctx, b->bytes);
+  if (b->h_fin) hipHostFree(b->h_fin);
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->stream) hipStreamDestroy(b->stream);
+  ladmm_case *c = b->c;
+  delete b;
+  case_unref(c);
+  return LADMM_OK;
+}
+
+int upload_tables(ladmm_batch *b, const uint64_t *ld_mask) {
+  ladmm_case *c = b->c;
+  const int G = c->G, kp = b->kp, k = b->k;
+  // per-plan LD point counts under the mask
+  std::vector<int64_t> cnt((size_t)(G + 1) * kp, 0);
+  for (int g = 0; g < G; ++g)
+    for (int j = 0; j < k; ++j) cnt[(size_t)g * kp + j] = c->counts[g];
+  if (ld_mask) {
+    for (int g = 0; g < G; ++g) {
+      if (c->groups[g].type != LADMM_PT_LD) continue;
+      for (int j = 0; j < k; ++j) cnt[(size_t)g * kp + j] = 0;
+    }
+    for (int pnt = 0; pnt < c->N; ++pnt) {
+      const int g = c->hgrp[pnt];
+      if (c->groups[g].type != LADMM_PT_LD) continue;
+      for (int j = 0; j < k; ++j) {
+        const uint64_t wd = ld_mask[(size_t)j * b->mask_words + (pnt >> 6)];
+        if ((wd >> (pnt & 63)) & 1ull) cnt[(size_t)g * kp + j]++;
+      }
+    }
+  }
+  std::vector<double> u((size_t)(G + 1) * kp, 0.0);
+  for (int g = 0; g < G; ++g) {
+    const ladmm_group &gr = c->groups[g];
+    for (int j = 0; j < k; ++j) {
+      double wt = 0.0;
+      switch (gr.type) {
+        case LADMM_PT_TS:
+        case LADMM_PT_TI: wt = b->w[j].w_t; break;
+        case LADMM_PT_RING: wt = b->w[j].w_r; break;
+        case LADMM_PT_LD: wt = b->w[j].w_ld; break;
+        default: wt = INFINITY;
+      }
+      double val;
+      if (gr.type == LADMM_PT_OAR) {
+        val = INFINITY;
+      } else {
+        const int64_t n = cnt[(size_t)g * kp + j];
+        val = n > 0 ? gr.share * wt / (double)n : 0.0;
+      }
+      u[(size_t)g * kp + j] = val;
+    }
+  }
+  if (c->precision == LADMM_F64) {
+    HIPC(hipMemcpy(b->utab, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> uf(u.begin(), u.end());
+    HIPC(hipMemcpy(b->utab, uf.data(), uf.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  std::vector<double> invrho(kp, 0.0), wbot(kp, 0.0), bbot((size_t)c->n_iso * kp, 0.0);
+  for (int j = 0; j < k; ++j) {
+    invrho[j] = 1.0 / b->rho[j];
+    wbot[j] = b->w[j].w_bot;
+    for (int i = 0; i < c->n_iso; ++i) bbot[(size_t)i * kp + j] = c->hE[c->ntp + i] * b->w[j].w_bot;
+  }
+  HIPC(hipMemcpy(b->invrho, invrho.data(), kp * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(b->wbot, wbot.data(), kp * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(b->bbot, bbot.data(), bbot.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (ld_mask) {
+    std::vector<uint64_t> m((size_t)kp * b->mask_words, 0);
+    std::memcpy(m.data(), ld_mask, (size_t)k * b->mask_words * sizeof(uint64_t));
+    HIPC(hipMemcpy(b->mask, m.data(), m.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+  }
+  HIPC(hipMemcpy(b->active, b->h_active.data(), kp * sizeof(int32_t), hipMemcpyHostToDevice));
+  return LADMM_OK;
+}
+
+int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const uint64_t *ld_mask,
+                      const double *rho, const ladmm_opts *opts, ladmm_batch **out) {
+  if (!c || !w || !opts || !out) return fail(LADMM_E_INVALID, "null argument");
+  if (k < 1) return fail(LADMM_E_INVALID, "k must be >= 1");
+  if (opts->max_iter < 0 || opts->check_every < 1)
+    return fail(LADMM_E_INVALID, "max_iter must be >= 0 and check_every >= 1");
+  for (int j = 0; j < k; ++j) {
+    const ladmm_weights &x = w[j];
+    if (!(x.w_bot > 0) || !std::isfinite(x.w_bot))
+      return fail(LADMM_E_INVALID, "plan " + std::to_string(j) + ": w_bot must be > 0");
+    if (!(x.w_t >= 0) || !(x.w_r >= 0) || !(x.w_ld >= 0) || !std::isfinite(x.w_t) ||
+        !std::isfinite(x.w_r) || !std::isfinite(x.w_ld))
+      return fail(LADMM_E_INVALID, "plan " + std::to_string(j) + ": weights must be finite and >= 0");
+    if (rho && (!(rho[j] > 0) || !std::isfinite(rho[j])))
+      return fail(LADMM_E_INVALID, "plan " + std::to_string(j) + ": rho must be > 0");
+  }
+  if (!rho && (!(opts->rho0 > 0) || !(opts->w0_bot > 0)))
+    return fail(LADMM_E_INVALID, "rho0 and w0_bot must be > 0");
+
+  if (c->destroyed) return fail(LADMM_E_STATE, "case has been destroyed");
+  ladmm_batch *b = new ladmm_batch();
+  b->c = c;
+  {
+    std::lock_guard<std::mutex> lk(c->ctx->mu);
+    c->refs++;
+  }
+  b->k = k;
+  b->kp = round_up(k, 32);
+  b->opts = *opts;
+  b->w.assign(w, w + k);
+  b->rho.resize(k);
+  for (int j = 0; j < k; ++j)
+    b->rho[j] = rho ? rho[j] : opts->rho0 * std::sqrt(opts->w0_bot / w[j].w_bot);
+  b->h_active.assign(b->kp, 0);
+  for (int j = 0; j < k; ++j) b->h_active[j] = 1;
+  b->status.assign(k, LADMM_PLAN_RUNNING);
+  b->iters.assign(k, 0);
+  b->rec.assign((size_t)k * kFinal, NAN);
+  b->mask_words = (c->Np + 63) / 64;
+
+  auto bad = [&](int rc) {
+    destroy_batch_impl(b);
+    return rc;
+  };
+#define B_RC(expr)           \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_) return bad(rc_); \
+  } while (0)
+#define B_HIP(call)                                                                    \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      fail(LADMM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return bad(LADMM_E_DEVICE);                                                      \
+    }                                                                                  \
+  } while (0)
+  B_HIP(hipSetDevice(c->ctx->device));
+  B_HIP(hipStreamCreate(&b->stream));
+  B_HIP(hipEventCreate(&b->ev0));
+  B_HIP(hipEventCreate(&b->ev1));
+  const size_t Tsz = c->precision == LADMM_F64 ? sizeof(double) : sizeof(float);
+  const int kp = b->kp;
+  void *p;
+  B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * Tsz)); b->q = p;
+  B_RC(batch_alloc(b, &p, (size_t)c->n_sec * kp * sizeof(double))); b->qs = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->q2 = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)(c->G + 1) * kp * Tsz)); b->utab = p;
+  if (ld_mask) {
+    B_RC(batch_alloc(b, &p, (size_t)kp * b->mask_words * sizeof(uint64_t)));
+    b->mask = (uint64_t *)p;
+  }
+  B_RC(batch_alloc(b, &p, kp * sizeof(double))); b->invrho = (double *)p;
+  B_RC(batch_alloc(b, &p, kp * sizeof(double))); b->wbot = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->n_iso * kp * sizeof(double))); b->bbot = (double *)p;
+  B_RC(batch_alloc(b, &p, kp * sizeof(int32_t))); b->active = (int32_t *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->nchunk1 * c->ntp * kp * Tsz)); b->P1 = p;
+  B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->r = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->nchunk2 * c->mAp * kp * sizeof(double))); b->P2 = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->vT = p;
+  B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->that = p;
+  b->admm_blocks = c->Np / kTileRows;
+  b->obj_blocks = c->Np / kTileRows;
+  b->post_blocks = (c->mAp + c->n_sec + 31) / 32;
+  B_RC(batch_alloc(b, &p, (size_t)b->admm_blocks * kAdmmStats * kp * sizeof(double))); b->admm_stats = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)b->post_blocks * kAdmmStats * kp * sizeof(double))); b->post_stats = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)b->obj_blocks * kObjStats * kp * sizeof(double))); b->obj_stats = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)kp * kFinal * sizeof(double))); b->fin = (double *)p;
+  B_HIP(hipHostMalloc((void **)&b->h_fin, (size_t)kp * kFinal * sizeof(double), hipHostMallocDefault));
+  B_HIP(hipMemsetAsync(b->q, 0, (size_t)c->Np * kp * Tsz, b->stream));
+  B_HIP(hipMemsetAsync(b->qs, 0, (size_t)c->n_sec * kp * sizeof(double), b->stream));
+  B_HIP(hipMemsetAsync(b->q2, 0, (size_t)c->mAp * kp * sizeof(double), b->stream));
+  B_HIP(hipStreamSynchronize(b->stream));
+  B_RC(upload_tables(b, ld_mask));
+#undef B_RC
+#undef B_HIP
+  *out = b;
+  return LADMM_OK;
+}
+
+// Event pair around one launch when profiling (start if begin, else end).
+int prof_mark(ladmm_batch *b, int kind, bool begin) {
+  if (!b->profiling) return LADMM_OK;
+  if (b->ev_used == b->ev_pool.size()) {
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    b->ev_pool.push_back(e);
+  }
+  if (begin) b->ev_kind.push_back(kind);
+  HIPC(hipEventRecord(b->ev_pool[b->ev_used++], b->stream));
+  return LADMM_OK;
+}
+
+// After the stream has completed: accumulate the recorded pairs.
+int prof_collect(ladmm_batch *b) {
+  for (size_t i = 0; i < b->ev_kind.size(); ++i) {
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, b->ev_pool[2 * i], b->ev_pool[2 * i + 1]));
+    b->kms[b->ev_kind[i]] += ms;
+    b->kcount[b->ev_kind[i]] += 1;
+  }
+  b->ev_kind.clear();
+  b->ev_used = 0;
+  return LADMM_OK;
+}
+
+#define PROF(kind, launch)                      \
+  do {                                          \
+    int rc_ = prof_mark(b, kind, true);         \
+    if (rc_) return rc_;                        \
+    HIPC(launch);                               \
+    rc_ = prof_mark(b, kind, false);            \
+    if (rc_) return rc_;                        \
+  } while (0)
+
+// One ADMM iteration; with `stats`, also the per-plan statistics after it.
+template <typename T>
+int iterate_once(ladmm_batch *b, bool stats) {
+  ladmm_case *c = b->c;
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  PointTable<T> pt = point_table<T>(b);
+  SmallArgs sa = small_args(b);
+  PROF(0, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->q, kp, (T *)b->P1, kp, c->ntp,
+                      kp, c->Np, c->nchunk1, &pt)));
+  PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+                           c->nchunk2, nullptr)));
+  PROF(3, (post<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->qs, b->q2, (T *)b->vT,
+                   stats ? b->post_stats : nullptr, &b->post_blocks)));
+  EpiArgs<T> ea{};
+  ea.q = (T *)b->q;
+  ea.ldq = kp;
+  ea.invrho = b->invrho;
+  ea.active = b->active;
+  ea.stats = b->admm_stats;
+  ea.nstat_cols = kp;
+  ea.pt = pt;
+  PROF(4, (gemm_nn<T>(s, stats ? EPI_ADMM_STATS : EPI_ADMM, (const T *)c->D, c->ntp,
+                      (const T *)b->vT, kp, c->Np, kp, c->ntp, ea)));
+  if (stats) {
+    PROF(6, (shot_scaled<T>(s, sa, b->q2, (T *)b->that)));
+    EpiArgs<T> eo = ea;
+    eo.stats = b->obj_stats;
+    PROF(5, (gemm_nn<T>(s, EPI_OBJ, (const T *)c->D, c->ntp, (const T *)b->that, kp, c->Np, kp,
+                        c->ntp, eo)));
+    FinalArgs fa;
+    fa.admm_stats = b->admm_stats;
+    fa.admm_blocks = b->admm_blocks;
+    fa.post_stats = b->post_stats;
+    fa.post_blocks = b->post_blocks;
+    fa.obj_stats = b->obj_stats;
+    fa.obj_blocks = b->obj_blocks;
+    fa.q2 = b->q2;
+    fa.E = c->E;
+    fa.invrho = b->invrho;
+    fa.wbot = b->wbot;
+    fa.L = c->L;
+    fa.cs = c->cs;
+    fa.kp = kp;
+    fa.out = b->fin;
+    PROF(7, (finalize(s, fa)));
+  }
+  return LADMM_OK;
+}
+
+int iterate_any(ladmm_batch *b, bool stats) {
+  return b->c->precision == LADMM_F64 ? iterate_once<double>(b, stats) : iterate_once<float>(b, stats);
+}
+
+// Run n iterations (the last one with statistics), update the host records and,
+// if `decide`, freeze plans that meet the stopping test.
+int run_chunk(ladmm_batch *b, int n, bool decide) {
+  if (n <= 0) return LADMM_OK;
+  int n_active = 0;
+  for (int j = 0; j < b->k; ++j) n_active += b->h_active[j] != 0;
+  HIPC(hipEventRecord(b->ev0, b->stream));
+  for (int i = 0; i < n; ++i) {
+    int rc = iterate_any(b, i == n - 1);
+    if (rc) return rc;
+  }
+  HIPC(hipEventRecord(b->ev1, b->stream));
+  HIPC(hipMemcpyAsync(b->h_fin, b->fin, (size_t)b->kp * kFinal * sizeof(double),
+                      hipMemcpyDeviceToHost, b->stream));
+  HIPC(hipStreamSynchronize(b->stream));
+  {
+    int rc = prof_collect(b);
+    if (rc) return rc;
+  }
+  float ms = 0.f;
+  HIPC(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  b->iterate_ms += ms;
+  b->plan_iters += (int64_t)n * n_active;
+  b->iters_run += n;
+  bool changed = false;
+  for (int j = 0; j < b->k; ++j) {
+    if (!b->h_active[j]) continue;
+    const double *f = b->h_fin + (size_t)j * kFinal;
+    std::memcpy(&b->rec[(size_t)j * kFinal], f, kFinal * sizeof(double));
+    b->iters[j] = b->iters_run;
+    bool bad = false;
+    for (int q = 0; q < kFinal; ++q) bad |= !std::isfinite(f[q]);
+    if (bad) {
+      b->status[j] = LADMM_PLAN_NUMERIC;
+      b->h_active[j] = 0;
+      changed = true;
+      continue;
+    }
+    if (decide && b->opts.tol_gap > 0 && f[2] <= b->opts.tol_gap && f[3] <= b->opts.tol_pri &&
+        f[4] <= b->opts.tol_dual) {
+      b->status[j] = LADMM_PLAN_CONVERGED;
+      b->h_active[j] = 0;
+      changed = true;
+    }
+  }
+  if (changed)
+    HIPC(hipMemcpy(b->active, b->h_active.data(), b->kp * sizeof(int32_t), hipMemcpyHostToDevice));
+  return LADMM_OK;
+}
+
+int run_impl(ladmm_batch *b) {
+  HIPC(hipSetDevice(b->c->ctx->device));
+  const int every = b->opts.check_every;
+  while (b->iters_run < b->opts.max_iter) {
+    bool any = false;
+    for (int j = 0; j < b->k; ++j) any |= b->h_active[j] != 0;
+    if (!any) break;
+    const int n = std::min(every, b->opts.max_iter - b->iters_run);
+    int rc = run_chunk(b, n, true);
+    if (rc) return rc;
+  }
+  for (int j = 0; j < b->k; ++j)
+    if (b->status[j] == LADMM_PLAN_RUNNING) b->status[j] = LADMM_PLAN_MAX_ITER;
+  return LADMM_OK;
+}
+
+int results_impl(ladmm_batch *b, ladmm_result *out) {
+  if (!out) return fail(LADMM_E_INVALID, "null result");
+  ladmm_case *c = b->c;
+  const int k = b->k;
+  if (out->t || out->bot) {
+    double *dt = nullptr;
+    HIPC(hipMalloc((void **)&dt, (size_t)k * c->n_t * sizeof(double)));
+    SmallArgs sa = small_args(b);
+    hipError_t e = extract_t(b->stream, sa, b->q2, dt, k);
+    std::vector<double> ht((size_t)k * c->n_t);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ht.data(), dt, ht.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(dt);
+    if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("extract: ") + hipGetErrorString(e));
+    if (out->t) std::memcpy(out->t, ht.data(), ht.size() * sizeof(double));
+    if (out->bot) {
+      for (int j = 0; j < k; ++j)
+        for (int i = 0; i < c->n_iso; ++i) {
+          double best = 0.0;
+          for (int s = 0; s < c->S; ++s) {
+            double sec = 0.0;
+            for (int cc = 0; cc < c->C; ++cc) sec += ht[(size_t)j * c->n_t + (i * c->S + s) * c->C + cc];
+            best = std::max(best, sec);
+          }
+          out->bot[(size_t)j * c->n_iso + i] = c->cs * best;
+        }
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    const double *f = &b->rec[(size_t)j * kFinal];
+    if (out->objective) out->objective[j] = f[0];
+    if (out->dual_obj) out->dual_obj[j] = f[1];
+    if (out->rel_gap) out->rel_gap[j] = f[2];
+    if (out->r_pri) out->r_pri[j] = f[3];
+    if (out->r_dual) out->r_dual[j] = f[4];
+    if (out->iters) out->iters[j] = b->iters[j];
+    if (out->plan_status) out->plan_status[j] = b->status[j];
+  }
+  return LADMM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ladmm_last_error(void) { return g_err.c_str(); }
+const char *ladmm_version(void) { return "ladmm 0.1 gfx950"; }
+
+int ladmm_ctx_create(int device, size_t hbm_budget_bytes, ladmm_ctx **out) {
+  if (!out) return fail(LADMM_E_INVALID, "null out");
+  int n = 0;
+  HIPC(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(LADMM_E_INVALID, "no such device");
+  HIPC(hipSetDevice(device));
+  ladmm_ctx *c = new ladmm_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return LADMM_OK;
+}
+
+int ladmm_ctx_destroy(ladmm_ctx *ctx) {
+  if (!ctx) return LADMM_OK;
+  bool now;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->destroyed = true;
+    now = ctx->refs == 0;
+  }
+  if (now) delete ctx;   // otherwise freed with its last case
+  return LADMM_OK;
+}
+
+size_t ladmm_ctx_used_bytes(const ladmm_ctx *ctx) { return ctx ? ctx->used : 0; }
+
+int ladmm_create_case(ladmm_ctx *ctx, const ladmm_case_desc *desc, ladmm_case **out) {
+  try {
+    return create_case_impl(ctx, desc, out);
+  } catch (const std::exception &e) {
+    return fail(LADMM_E_NOMEM, e.what());
+  }
+}
+
+int ladmm_destroy_case(ladmm_case *c) {
+  if (!c) return LADMM_OK;
+  bool now;
+  {
+    std::lock_guard<std::mutex> lk(c->ctx->mu);
+    c->destroyed = true;
+    now = c->refs == 0;
+  }
+  if (now) case_free(c);   // otherwise freed with its last batch
+  return LADMM_OK;
+}
+
+int ladmm_case_scaling(const ladmm_case *c, double *E, double *beta) {
+  if (!c) return fail(LADMM_E_STATE, "null case");
+  if (E) {
+    for (int t = 0; t < c->n_t; ++t) E[t] = c->hE[t];
+    for (int i = 0; i < c->n_iso; ++i) E[c->n_t + i] = c->hE[c->ntp + i];
+  }
+  if (beta) *beta = c->beta;
+  return LADMM_OK;
+}
+
+int ladmm_case_schur(const ladmm_case *c, double *S, double *S_inv) {
+  if (!c) return fail(LADMM_E_STATE, "null case");
+  HIPC(hipSetDevice(c->ctx->device));
+  const int mA = c->n_t + c->n_iso;
+  std::vector<double> h((size_t)c->mAp * c->mAp);
+  auto idx = [&](int a) { return a < c->n_t ? a : c->ntp + (a - c->n_t); };
+  for (int w = 0; w < 2; ++w) {
+    double *dst = w == 0 ? S : S_inv;
+    if (!dst) continue;
+    HIPC(hipMemcpy(h.data(), w == 0 ? c->Smat : c->Sinv, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int a = 0; a < mA; ++a)
+      for (int bb = 0; bb < mA; ++bb) dst[(size_t)a * mA + bb] = h[(size_t)idx(a) * c->mAp + idx(bb)];
+  }
+  return LADMM_OK;
+}
+
+double ladmm_case_setup_ms(const ladmm_case *c) { return c ? c->setup_ms : 0.0; }
+
+int ladmm_batch_create(ladmm_case *c, int32_t k, const ladmm_weights *w, const uint64_t *ld_mask,
+                       const double *rho, const ladmm_opts *opts, ladmm_batch **out) {
+  try {
+    return create_batch_impl(c, k, w, ld_mask, rho, opts, out);
+  } catch (const std::exception &e) {
+    return fail(LADMM_E_NOMEM, e.what());
+  }
+}
+
+int ladmm_batch_destroy(ladmm_batch *b) { return destroy_batch_impl(b); }
+
+int ladmm_batch_iterate(ladmm_batch *b, int32_t iters) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (iters < 0) return fail(LADMM_E_INVALID, "iters must be >= 0");
+  HIPC(hipSetDevice(b->c->ctx->device));
+  return run_chunk(b, iters, false);
+}
+
+int ladmm_batch_run(ladmm_batch *b) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  return run_impl(b);
+}
+
+int ladmm_batch_results(ladmm_batch *b, ladmm_result *out) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  HIPC(hipSetDevice(b->c->ctx->device));
+  return results_impl(b, out);
+}
+
+int ladmm_batch_export(ladmm_batch *b, double *z1, double *y1, double *z2, double *y2) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  ladmm_case *c = b->c;
+  HIPC(hipSetDevice(c->ctx->device));
+  const int k = b->k, kp = b->kp, N = c->N, nA = N + c->n_sec, mA = c->n_t + c->n_iso;
+  std::vector<double> hz((size_t)N * k), hy((size_t)N * k);
+  double *dz = nullptr, *dy = nullptr;
+  HIPC(hipMalloc((void **)&dz, hz.size() * sizeof(double)));
+  hipError_t e = hipMalloc((void **)&dy, hy.size() * sizeof(double));
+  if (e == hipSuccess) {
+    if (c->precision == LADMM_F64)
+      e = export_points<double>(b->stream, (const double *)b->q, kp, point_table<double>(b), N, k, dz, dy);
+    else
+      e = export_points<float>(b->stream, (const float *)b->q, kp, point_table<float>(b), N, k, dz, dy);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hz.data(), dz, hz.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), dy, hy.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  hipFree(dz);
+  if (dy) hipFree(dy);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("export: ") + hipGetErrorString(e));
+  std::vector<double> qs((size_t)c->n_sec * kp), q2((size_t)c->mAp * kp), bb((size_t)c->n_iso * kp);
+  HIPC(hipMemcpy(qs.data(), b->qs, qs.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(q2.data(), b->q2, q2.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(bb.data(), b->bbot, bb.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int p = 0; p < N; ++p)
+    for (int j = 0; j < k; ++j) {
+      if (z1) z1[(size_t)p * k + j] = hz[(size_t)p * k + j];
+      if (y1) y1[(size_t)p * k + j] = hy[(size_t)p * k + j];
+    }
+  for (int sct = 0; sct < c->n_sec; ++sct)
+    for (int j = 0; j < k; ++j) {
+      const double q = qs[(size_t)sct * kp + j], z = std::max(q, 0.0);
+      if (z1) z1[(size_t)(N + sct) * k + j] = z;
+      if (y1) y1[(size_t)(N + sct) * k + j] = q - z;
+    }
+  for (int a = 0; a < mA; ++a) {
+    const int row = a < c->n_t ? a : c->ntp + (a - c->n_t);
+    for (int j = 0; j < k; ++j) {
+      const double bnd = a < c->n_t ? 0.0 : bb[(size_t)(a - c->n_t) * kp + j];
+      const double q = q2[(size_t)row * kp + j], z = std::min(q, bnd);
+      if (z2) z2[(size_t)a * k + j] = z;
+      if (y2) y2[(size_t)a * k + j] = q - z;
+    }
+  }
+  (void)nA;
+  return LADMM_OK;
+}
+
+int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const double *z2,
+                       const double *y2) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (!z1 || !y1 || !z2 || !y2) return fail(LADMM_E_INVALID, "import needs z1, y1, z2, y2");
+  ladmm_case *c = b->c;
+  HIPC(hipSetDevice(c->ctx->device));
+  const int k = b->k, kp = b->kp, N = c->N, mA = c->n_t + c->n_iso;
+  double *dz = nullptr, *dy = nullptr;
+  HIPC(hipMalloc((void **)&dz, (size_t)N * k * sizeof(double)));
+  hipError_t e = hipMalloc((void **)&dy, (size_t)N * k * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(dz, z1, (size_t)N * k * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dy, y1, (size_t)N * k * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    if (c->precision == LADMM_F64)
+      e = import_points<double>(b->stream, (double *)b->q, kp, N, k, dz, dy);
+    else
+      e = import_points<float>(b->stream, (float *)b->q, kp, N, k, dz, dy);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  hipFree(dz);
+  if (dy) hipFree(dy);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("import: ") + hipGetErrorString(e));
+  std::vector<double> qs((size_t)c->n_sec * kp, 0.0), q2((size_t)c->mAp * kp, 0.0);
+  for (int sct = 0; sct < c->n_sec; ++sct)
+    for (int j = 0; j < k; ++j)
+      qs[(size_t)sct * kp + j] = z1[(size_t)(N + sct) * k + j] + y1[(size_t)(N + sct) * k + j];
+  for (int a = 0; a < mA; ++a) {
+    const int row = a < c->n_t ? a : c->ntp + (a - c->n_t);
+    for (int j = 0; j < k; ++j) q2[(size_t)row * kp + j] = z2[(size_t)a * k + j] + y2[(size_t)a * k + j];
+  }
+  HIPC(hipMemcpy(b->qs, qs.data(), qs.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(b->q2, q2.data(), q2.size() * sizeof(double), hipMemcpyHostToDevice));
+  return LADMM_OK;
+}
+
+int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  b->profiling = on != 0;
+  for (int i = 0; i < LADMM_N_KERNEL_CLASSES; ++i) {
+    b->kms[i] = 0.0;
+    b->kcount[i] = 0;
+  }
+  return LADMM_OK;
+}
+
+int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  for (int i = 0; i < LADMM_N_KERNEL_CLASSES; ++i) {
+    if (ms_total) ms_total[i] = b->kms[i];
+    if (launches) launches[i] = b->kcount[i];
+  }
+  return LADMM_OK;
+}
+
+int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_iterations) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (iterate_ms) *iterate_ms = b->iterate_ms;
+  if (plan_iterations) *plan_iterations = b->plan_iters;
+  return LADMM_OK;
+}
+
+int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double d_ld,
+                        double delta, uint64_t *vol_bits) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (n_vox < 1 || !phi_vox || !vol_bits || !(delta > 0) || !std::isfinite(d_ld))
+    return fail(LADMM_E_INVALID, "ld_band: bad arguments");
+  if (n_vox > (int64_t)1 << 30) return fail(LADMM_E_INVALID, "ld_band: too many voxels");
+  ladmm_case *c = b->c;
+  HIPC(hipSetDevice(c->ctx->device));
+  const int nv = (int)n_vox, nvp = round_up(nv, kTileRows), W = (nv + 63) / 64;
+  const size_t nd = (size_t)nv * c->n_t;
+  for (size_t e = 0; e < nd; ++e)
+    if (!(phi_vox[e] >= 0.0) || !std::isfinite(phi_vox[e]))
+      return fail(LADMM_E_INVALID, "ld_band: dose rates must be finite and >= 0");
+  std::vector<double> hp((size_t)nvp * c->ntp, 0.0);
+  for (int v = 0; v < nv; ++v)
+    std::memcpy(&hp[(size_t)v * c->ntp], phi_vox + (size_t)v * c->n_t, c->n_t * sizeof(double));
+  double *dphi = nullptr, *dt = nullptr, *dd = nullptr;
+  uint64_t *dbits = nullptr;
+  hipError_t e = hipMalloc((void **)&dphi, hp.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&dt, (size_t)c->ntp * b->kp * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&dd, (size_t)nvp * b->kp * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&dbits, (size_t)b->k * W * sizeof(uint64_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dphi, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, b->stream);
+  SmallArgs sa = small_args(b);
+  if (e == hipSuccess) e = shot_times_matrix(b->stream, sa, b->q2, dt);
+  if (e == hipSuccess) {
+    EpiArgs<double> ea{};
+    ea.C = dd;
+    ea.ldc = b->kp;
+    e = gemm_nn<double>(b->stream, EPI_STORE, dphi, c->ntp, dt, b->kp, nvp, b->kp, c->ntp, ea);
+  }
+  if (e == hipSuccess) e = band_bits(b->stream, dd, b->kp, nv, b->k, d_ld, d_ld + delta, dbits);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(vol_bits, dbits, (size_t)b->k * W * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (dphi) hipFree(dphi);
+  if (dt) hipFree(dt);
+  if (dd) hipFree(dd);
+  if (dbits) hipFree(dbits);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("ld_band: ") + hipGetErrorString(e));
+  return LADMM_OK;
+}
+
+int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint64_t *vol_bits,
+                           const int32_t *n_ld, uint64_t seed, int64_t *P, int64_t *nP,
+                           uint64_t *masks) {
+  if (!ctx) return fail(LADMM_E_STATE, "null context");
+  if (k < 0 || n_vox < 1 || !nP || (k > 0 && (!vol_bits || !n_ld || !P || !masks)))
+    return fail(LADMM_E_INVALID, "select_ld_points: bad arguments");
+  if (n_vox > (int64_t)1 << 31) return fail(LADMM_E_INVALID, "select_ld_points: too many voxels");
+  const int W = (int)((n_vox + 63) / 64);
+  if (k == 0) {
+    *nP = 0;
+    return LADMM_OK;
+  }
+  // bits past n_vox must be clear
+  if (n_vox % 64)
+    for (int j = 0; j < k; ++j)
+      if (vol_bits[(size_t)j * W + W - 1] >> (n_vox % 64))
+        return fail(LADMM_E_INVALID, "select_ld_points: bits set past n_vox");
+  HIPC(hipSetDevice(ctx->device));
+  Alg1Work wk{};
+  std::vector<void *> mem;
+  hipError_t e = hipSuccess;
+  auto get = [&](void **p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 8);
+    if (e == hipSuccess) mem.push_back(*p);
+  };
+  const size_t wb = (size_t)W * sizeof(uint64_t);
+  get((void **)&wk.Vu, wb); get((void **)&wk.pu, wb); get((void **)&wk.pt, wb);
+  get((void **)&wk.nw, wb); get((void **)&wk.po, wb); get((void **)&wk.tmp, wb);
+  get((void **)&wk.uni, wb); get((void **)&wk.keys, wb * 64); get((void **)&wk.pj, wb * k);
+  get((void **)&wk.vsize, (size_t)k * sizeof(int64_t)); get((void **)&wk.order, (size_t)k * sizeof(int32_t));
+  get((void **)&wk.offs, (size_t)W * sizeof(int64_t));
+  uint64_t *dvols = nullptr, *dmasks = nullptr;
+  int32_t *dn = nullptr;
+  int64_t *dP = nullptr, *dnP = nullptr;
+  get((void **)&dvols, wb * k); get((void **)&dmasks, wb * k); get((void **)&dn, (size_t)k * sizeof(int32_t));
+  get((void **)&dP, (size_t)n_vox * sizeof(int64_t)); get((void **)&dnP, sizeof(int64_t));
+  hipStream_t s = nullptr;
+  if (e == hipSuccess) e = hipStreamCreate(&s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dvols, vol_bits, wb * k, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dn, n_ld, (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = alg1_select(s, k, n_vox, dvols, dn, seed, wk, dP, dnP, dmasks, W);
+  int64_t hn = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hn, dnP, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && hn > 0)
+    e = hipMemcpyAsync(P, dP, (size_t)hn * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(masks, dmasks, wb * k, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (void *p : mem) hipFree(p);
+  if (s) hipStreamDestroy(s);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("select_ld_points: ") + hipGetErrorString(e));
+  *nP = hn;
+  return LADMM_OK;
+}
+
+int ladmm_solve_batch(ladmm_case *c, int32_t k, const ladmm_weights *w, const uint64_t *ld_mask,
+                      const ladmm_opts *opts, ladmm_result *out) {
+  ladmm_batch *b = nullptr;
+  int rc = ladmm_batch_create(c, k, w, ld_mask, nullptr, opts, &b);
+  if (rc) return rc;
+  rc = ladmm_batch_run(b);
+  if (rc == LADMM_OK) rc = ladmm_batch_results(b, out);
+  destroy_batch_impl(b);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal launchers of the HIP kernels (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ladmm {
+
+// Tile sizes shared by the launchers and the host-side padding rules.
+constexpr int kTileRows = 64;     // rows (points, shots) of a GEMM tile
+constexpr int kSmallAlign = 64;   // padding of the shot / small-row dimension
+
+// Layout of the small (m_A) vectors: shot rows t in [0, ntp) (t < n_t real),
+// BOT rows at ntp + i (i < n_iso), zero padding up to mAp.
+struct SmallLayout {
+  int n_t, ntp, n_iso, mAp, n_sec, S, C;
+};
+
+// Per-point description used by the prologue / epilogues.
+template <typename T>
+struct PointTable {
+  const int32_t *grp;     // Np: group id (G = padding group)
+  const T *sig;           // Np: +1 target, -1 other, 0 padding
+  const int32_t *is_ld;   // per group: 1 if low-dose group
+  const int32_t *is_oar;  // per group: 1 if OAR group
+  const T *utab;          // (G+1) x ldu: u of (group, plan); +inf for OAR
+  int ldu;
+  const uint64_t *mask;   // NULL or kp rows x mask_words: low-dose membership
+  int mask_words;
+};
+
+// ---- generic products -----------------------------------------------------
+// P[z][m][n] = sum over rows k of chunk z of A[k][m] * B[k][n]   (A: K x M, B: K x N)
+// With the ADMM prologue, B is replaced by W = 2 clip(q, 0, u) - q.
+template <typename T>
+hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
+                   int M, int N, int K, int nchunk, const PointTable<T> *pro);
+// P[z][m][n] for FP64 accumulation of FP64 operands is the T = double case.
+
+// Epilogues of C = A B (A: M x K row-major, B: K x N row-major).
+enum { EPI_STORE = 0, EPI_ADMM = 1, EPI_ADMM_STATS = 2, EPI_OBJ = 3 };
+constexpr int kAdmmStats = 6;   // (x-z)^2, x^2, z^2, (z-zprev)^2, y^2, c'z
+constexpr int kObjStats = 2;    // hinge sum, OAR dose ratio max
+template <typename T>
+struct EpiArgs {
+  T *C; int ldc;                   // EPI_STORE output
+  T *q; int ldq;                   // EPI_ADMM: iterate q (in place)
+  const double *invrho;            // per plan 1/rho
+  const int32_t *active;           // per plan
+  double *stats; int nstat_cols;   // partial stats [blockIdx.x][stat][nstat_cols]
+  PointTable<T> pt;
+};
+template <typename T>
+hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb,
+                   int M, int N, int K, const EpiArgs<T> &ea);
+
+// ---- setup ------------------------------------------------------------------
+// Dt[p][t] = sig[p] * phi[p][t] / thr[p]; zero padding rows/cols (FP64).
+hipError_t scale_dose(hipStream_t s, const double *phi, int N, int n_t, const double *sig,
+                      const double *inv_thr, double *Dt, int Np, int ntp);
+// out[p][t] = (T)(Dt[p][t] * E[t])
+template <typename T>
+hipError_t scale_columns(hipStream_t s, const double *Dt, const double *E, T *out, int Np, int ntp);
+// sum of nchunk partials [z][rows][cols] (ld) -> out (double)
+template <typename T>
+hipError_t reduce_partials(hipStream_t s, const T *P, size_t zstride, int nchunk, int rows, int cols,
+                           int ld, double *out, int ldo);
+// E and S from K = Dt' Dt (ntp x ntp); S is mAp x mAp.
+hipError_t assemble_schur(hipStream_t s, const double *K, int ldk, const SmallLayout &L,
+                          double cs, double beta, double e_bot, int row_normalize,
+                          double *E, double *S);
+// Blocked Cholesky S = L L' in place (lower), n x n, ld; info set to 1 on failure.
+hipError_t cholesky(hipStream_t s, double *S, int n, int ld, int *dinfo);
+// X = L^-1 (lower triangular), n x n.
+hipError_t tri_inverse(hipStream_t s, const double *L, double *X, int n, int ld);
+
+// ---- per iteration ----------------------------------------------------------
+struct SmallArgs {
+  SmallLayout L;
+  const double *E;      // mAp
+  const double *gvec;   // ntp
+  double beta, cs;
+  const double *invrho; // kp
+  const double *bbot;   // n_iso x kp: scaled BOT bound E_bot * w_BOT
+  const int32_t *active;
+  int kp;
+};
+// r = A_s W + g / rho - (2 clip(q2) - q2), from the GEMM1 partials.
+template <typename T>
+hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
+               const double *qs, const double *q2, double *r);
+// v = sum of Sinv*r partials; q2 <- v + Pi(q2); qs <- max(qs,0) - (A_sec' v);
+// vT <- (T) v_top; optional stats partials [block][kAdmmStats][kp].
+template <typename T>
+hipError_t post(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
+                double *qs, double *q2, T *vT, double *stats, int *nblocks_out);
+// that = rho * max(q2_top, 0) (shot times over E), as T.
+template <typename T>
+hipError_t shot_scaled(hipStream_t s, const SmallArgs &a, const double *q2, T *that);
+// Per plan: F, c'z1, gap, r_pri, r_dual, oar ratio, from the partial stats.
+struct FinalArgs {
+  const double *admm_stats; int admm_blocks;
+  const double *post_stats; int post_blocks;
+  const double *obj_stats; int obj_blocks;
+  const double *q2; const double *E; const double *invrho; const double *wbot;
+  SmallLayout L; double cs; int kp;
+  double *out;   // kp x kFinal
+};
+constexpr int kFinal = 8;   // F, c'z, gap, r_pri, r_dual, oar_ratio, bot_sum, hinge
+hipError_t finalize(hipStream_t s, const FinalArgs &a);
+// t[j][t] = E_t rho_j max(q2_t, 0) (k x n_t, double)
+hipError_t extract_t(hipStream_t s, const SmallArgs &a, const double *q2, double *t, int k);
+
+// t as a shot-major matrix for products with dose rates: out[t][j] = E_t rho_j max(q2_t, 0)
+// (ntp x kp, zero padding).
+hipError_t shot_times_matrix(hipStream_t s, const SmallArgs &a, const double *q2, double *out);
+
+// ---- Algorithm 1 and the low-dose band -----------------------------------------
+struct Alg1Work {
+  uint64_t *Vu, *pu, *pt, *nw, *po, *tmp, *uni;   // W words each
+  uint64_t *keys;                                  // W * 64
+  uint64_t *pj;                                    // k * W
+  int64_t *vsize;                                  // k
+  int32_t *order;                                  // k
+  int64_t *offs;                                   // W
+};
+// vols: k x W words (device); P: n_vox capacity; masks: k rows of ldm >= W words.
+hipError_t alg1_select(hipStream_t s, int k, int64_t n_vox, const uint64_t *vols, const int32_t *n_ld,
+                       uint64_t seed, Alg1Work &wk, int64_t *P, int64_t *nP, uint64_t *masks, int ldm);
+// bits[j][v / 64] bit v % 64 = (lo <= d[v][j] < hi), d: n_vox rows of ldd.
+hipError_t band_bits(hipStream_t s, const double *d, int ldd, int n_vox, int k, double lo, double hi,
+                     uint64_t *bits);
+
+// ---- state conversion ---------------------------------------------------------
+template <typename T>
+hipError_t export_points(hipStream_t s, const T *q, int ldq, const PointTable<T> &pt, int N, int k,
+                         double *z, double *y);
+template <typename T>
+hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const double *z, const double *y);
+
+}  // namespace ladmm

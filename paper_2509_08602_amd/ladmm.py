@@ -1,0 +1,393 @@
+"""Python binding of libladmm (ctypes).  Argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts NumPy
+arrays to the C structures of include/ladmm.h and back.  There is no fallback:
+if the library is not built, importing works but the first call raises.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libladmm.so")
+
+OK, PENDING = 0, 1
+E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_CANCELLED = -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+PT_TS, PT_TI, PT_RING, PT_LD, PT_OAR = 0, 1, 2, 3, 4
+PLAN_CONVERGED, PLAN_MAX_ITER, PLAN_NUMERIC, PLAN_RUNNING = 0, 1, 2, 3
+PRECISIONS = {"f64": F64, "f32": F32}
+
+
+class LadmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ladmm error {code}: {msg}")
+        self.code = code
+
+
+class _Group(C.Structure):
+    _fields_ = [("type", C.c_int32), ("structure", C.c_int32), ("threshold", C.c_double),
+                ("share", C.c_double)]
+
+
+class _CaseDesc(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("n_iso", C.c_int32), ("n_sectors", C.c_int32),
+                ("n_collimators", C.c_int32), ("dose", C.POINTER(C.c_double)),
+                ("point_group", C.POINTER(C.c_int32)), ("n_groups", C.c_int32),
+                ("groups", C.POINTER(_Group)), ("prescription_mean", C.c_double),
+                ("phi_cal", C.c_double), ("precision", C.c_int32), ("row_normalize", C.c_int32),
+                ("beta", C.c_double), ("beta_denominator", C.c_double)]
+
+
+class _Weights(C.Structure):
+    _fields_ = [("w_t", C.c_double), ("w_r", C.c_double), ("w_ld", C.c_double),
+                ("w_bot", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("tol_gap", C.c_double),
+                ("tol_pri", C.c_double), ("tol_dual", C.c_double), ("rho0", C.c_double),
+                ("w0_bot", C.c_double)]
+
+
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+
+
+class _Result(C.Structure):
+    _fields_ = [("t", _DP), ("bot", _DP), ("objective", _DP), ("dual_obj", _DP),
+                ("rel_gap", _DP), ("r_pri", _DP), ("r_dual", _DP), ("iters", _IP),
+                ("plan_status", _IP)]
+
+
+_lib = None
+_EXITING = False
+
+
+@atexit.register
+def _at_exit():
+    # Handles still alive at interpreter exit are left to the process teardown:
+    # calling into the HIP runtime from finalizers after this point is unsafe.
+    global _EXITING
+    _EXITING = True
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ladmm_ctx_create": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "ladmm_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "ladmm_ctx_used_bytes": (C.c_size_t, [C.c_void_p]),
+    "ladmm_create_case": (C.c_int, [C.c_void_p, C.POINTER(_CaseDesc), C.POINTER(C.c_void_p)]),
+    "ladmm_destroy_case": (C.c_int, [C.c_void_p]),
+    "ladmm_case_scaling": (C.c_int, [C.c_void_p, _DP, _DP]),
+    "ladmm_case_schur": (C.c_int, [C.c_void_p, _DP, _DP]),
+    "ladmm_case_setup_ms": (C.c_double, [C.c_void_p]),
+    "ladmm_batch_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_Weights),
+                                     C.POINTER(C.c_uint64), _DP, C.POINTER(_Opts),
+                                     C.POINTER(C.c_void_p)]),
+    "ladmm_batch_destroy": (C.c_int, [C.c_void_p]),
+    "ladmm_batch_iterate": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ladmm_batch_run": (C.c_int, [C.c_void_p]),
+    "ladmm_batch_results": (C.c_int, [C.c_void_p, C.POINTER(_Result)]),
+    "ladmm_batch_export": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
+    "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
+    "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
+    "ladmm_batch_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ladmm_batch_kernel_times": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
+    "ladmm_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_Weights),
+                                    C.POINTER(C.c_uint64), C.POINTER(_Opts), C.POINTER(_Result)]),
+    "ladmm_batch_ld_band": (C.c_int, [C.c_void_p, C.c_int64, _DP, C.c_double, C.c_double,
+                                      C.POINTER(C.c_uint64)]),
+    "ladmm_select_ld_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_uint64),
+                                         _IP, C.c_uint64, C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ladmm_last_error": (C.c_char_p, []),
+    "ladmm_version": (C.c_char_p, []),
+}
+
+
+def library():
+    """Load libladmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2509_08602_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise LadmmError(rc, library().ladmm_last_error().decode())
+    return rc
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+@dataclasses.dataclass
+class Options:
+    """Solver options (see ladmm_opts in include/ladmm.h)."""
+    max_iter: int = 3000
+    check_every: int = 50
+    tol_gap: float = 1e-4
+    tol_pri: float = 1e-4
+    tol_dual: float = 1e-4
+    rho0: float = 1000.0
+    w0_bot: float = 1e-3
+
+    def c(self):
+        return _Opts(int(self.max_iter), int(self.check_every), float(self.tol_gap),
+                     float(self.tol_pri), float(self.tol_dual), float(self.rho0),
+                     float(self.w0_bot))
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self._h = C.c_void_p()
+        _check(library().ladmm_ctx_create(device, hbm_budget, C.byref(self._h)))
+
+    @property
+    def used_bytes(self):
+        return int(library().ladmm_ctx_used_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            library().ladmm_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        if _EXITING:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Case:
+    """A resident case: dose matrix, Schur complement factor and inverse in HBM."""
+
+    def __init__(self, ctx: Context, dose, point_group, groups, n_iso, n_sectors=8,
+                 n_collimators=3, prescription_mean=20.0, phi_cal=3.0, precision="f64",
+                 row_normalize=True, beta=None, beta_denominator=2000.0):
+        self.ctx = ctx
+        dose = np.ascontiguousarray(dose, dtype=np.float64)
+        pg = np.ascontiguousarray(point_group, dtype=np.int32)
+        garr = (_Group * len(groups))(*[_Group(int(t), int(s), float(th), float(sh))
+                                        for (t, s, th, sh) in groups])
+        self.n_points, self.n_t = dose.shape
+        self.n_iso, self.n_sectors, self.n_collimators = int(n_iso), int(n_sectors), int(n_collimators)
+        self.precision = precision
+        desc = _CaseDesc(self.n_points, self.n_iso, self.n_sectors, self.n_collimators,
+                         dose.ctypes.data_as(_DP), pg.ctypes.data_as(_IP), len(groups), garr,
+                         float(prescription_mean), float(phi_cal), PRECISIONS[precision],
+                         1 if row_normalize else 0, float(beta) if beta else 0.0,
+                         float(beta_denominator))
+        self._h = C.c_void_p()
+        _check(library().ladmm_create_case(ctx._h, C.byref(desc), C.byref(self._h)))
+
+    @classmethod
+    def from_case(cls, ctx, case, precision="f64", **kw):
+        """Marshal any object with the fields of a synthetic case (dose, group, ...)."""
+        groups = [(g.type, g.structure, g.threshold, g.share) for g in case.groups]
+        return cls(ctx, case.dose, case.group, groups, case.n_iso, case.n_sectors,
+                   case.n_collimators, case.prescription_mean, case.phi_cal, precision, **kw)
+
+    @property
+    def m_A(self):
+        return self.n_t + self.n_iso
+
+    def scaling(self):
+        E = np.empty(self.m_A)
+        beta = C.c_double()
+        _check(library().ladmm_case_scaling(self._h, _dptr(E), C.byref(beta)))
+        return E, beta.value
+
+    def schur(self):
+        S = np.empty((self.m_A, self.m_A))
+        Si = np.empty((self.m_A, self.m_A))
+        _check(library().ladmm_case_schur(self._h, _dptr(S), _dptr(Si)))
+        return S, Si
+
+    @property
+    def setup_ms(self):
+        return float(library().ladmm_case_setup_ms(self._h))
+
+    def close(self):
+        if self._h:
+            library().ladmm_destroy_case(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        if _EXITING:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _weights(w):
+    w = np.atleast_2d(np.asarray(w, np.float64))
+    arr = (_Weights * w.shape[0])(*[_Weights(*map(float, row[:4])) for row in w])
+    return arr, w.shape[0]
+
+
+def _mask_words(mask, n_points):
+    """k x N bool (or already-packed k x words uint64) -> contiguous uint64 words."""
+    if mask is None:
+        return None
+    mask = np.asarray(mask)
+    if mask.dtype == np.uint64:
+        return np.ascontiguousarray(mask)
+    k = mask.shape[0]
+    nw = (n_points + 63) // 64
+    padded = np.zeros((k, nw * 64), bool)
+    padded[:, :mask.shape[1]] = mask
+    bits = padded.reshape(k, nw, 64).astype(np.uint64) << np.arange(64, dtype=np.uint64)
+    return np.ascontiguousarray(np.bitwise_or.reduce(bits, axis=2))
+
+
+class Batch:
+    """k plans of one case with their iterates resident in HBM."""
+
+    def __init__(self, case: Case, weights, ld_mask=None, rho=None, opts: Options | None = None):
+        self.case = case
+        self.opts = opts or Options()
+        self._w, self.k = _weights(weights)
+        self._mask = _mask_words(ld_mask, case.n_points)
+        rho_arr = None if rho is None else np.ascontiguousarray(rho, np.float64)
+        self._h = C.c_void_p()
+        mp = self._mask.ctypes.data_as(C.POINTER(C.c_uint64)) if self._mask is not None else None
+        _check(library().ladmm_batch_create(case._h, self.k, self._w, mp, _dptr(rho_arr),
+                                            C.byref(self.opts.c()), C.byref(self._h)))
+
+    def iterate(self, n: int):
+        _check(library().ladmm_batch_iterate(self._h, int(n)))
+
+    def run(self):
+        _check(library().ladmm_batch_run(self._h))
+
+    def results(self, with_t=True):
+        k, c = self.k, self.case
+        out = dict(objective=np.empty(k), dual_obj=np.empty(k), rel_gap=np.empty(k),
+                   r_pri=np.empty(k), r_dual=np.empty(k), iters=np.empty(k, np.int32),
+                   plan_status=np.empty(k, np.int32))
+        if with_t:
+            out["t"] = np.empty((k, c.n_t))
+            out["bot"] = np.empty((k, c.n_iso))
+        r = _Result(_dptr(out.get("t")), _dptr(out.get("bot")), _dptr(out["objective"]),
+                    _dptr(out["dual_obj"]), _dptr(out["rel_gap"]), _dptr(out["r_pri"]),
+                    _dptr(out["r_dual"]), out["iters"].ctypes.data_as(_IP),
+                    out["plan_status"].ctypes.data_as(_IP))
+        _check(library().ladmm_batch_results(self._h, C.byref(r)))
+        return out
+
+    def export(self):
+        c, k = self.case, self.k
+        nA = c.n_points + c.n_iso * c.n_sectors
+        z1, y1 = np.empty((nA, k)), np.empty((nA, k))
+        z2, y2 = np.empty((c.m_A, k)), np.empty((c.m_A, k))
+        _check(library().ladmm_batch_export(self._h, _dptr(z1), _dptr(y1), _dptr(z2), _dptr(y2)))
+        return z1, y1, z2, y2
+
+    def load(self, z1, y1, z2, y2):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (z1, y1, z2, y2)]
+        _check(library().ladmm_batch_import(self._h, *[_dptr(a) for a in arrs]))
+
+    def timing(self):
+        ms = C.c_double()
+        pit = C.c_int64()
+        _check(library().ladmm_batch_timing(self._h, C.byref(ms), C.byref(pit)))
+        return ms.value, pit.value
+
+    KERNEL_CLASSES = ("gemm1", "rhs", "schur_solve", "post", "gemm2", "objective",
+                      "shot_scale", "finalize")
+
+    def set_profiling(self, on=True):
+        _check(library().ladmm_batch_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        """{class: (total ms, launches)} accumulated while profiling was on."""
+        ms = np.zeros(len(self.KERNEL_CLASSES))
+        n = np.zeros(len(self.KERNEL_CLASSES), np.int64)
+        _check(library().ladmm_batch_kernel_times(self._h, _dptr(ms),
+                                                  n.ctypes.data_as(C.POINTER(C.c_int64))))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    def ld_band(self, phi_vox, d_ld, delta, packed=False):
+        """Low-dose band of every plan at the candidate voxels (k x n_vox bool)."""
+        phi = np.ascontiguousarray(phi_vox, np.float64)
+        n_vox = phi.shape[0]
+        W = (n_vox + 63) // 64
+        bits = np.zeros((self.k, W), np.uint64)
+        _check(library().ladmm_batch_ld_band(self._h, n_vox, _dptr(phi), float(d_ld), float(delta),
+                                             bits.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return bits if packed else unpack(bits, n_vox)
+
+    def close(self):
+        if self._h:
+            library().ladmm_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        if _EXITING:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(case: Case, weights, ld_mask=None, opts: Options | None = None):
+    """ladmm_solve_batch: run k plans to convergence and return their results."""
+    w, k = _weights(weights)
+    mask = _mask_words(ld_mask, case.n_points)
+    mp = mask.ctypes.data_as(C.POINTER(C.c_uint64)) if mask is not None else None
+    o = (opts or Options()).c()
+    out = dict(t=np.empty((k, case.n_t)), bot=np.empty((k, case.n_iso)), objective=np.empty(k),
+               dual_obj=np.empty(k), rel_gap=np.empty(k), r_pri=np.empty(k), r_dual=np.empty(k),
+               iters=np.empty(k, np.int32), plan_status=np.empty(k, np.int32))
+    r = _Result(_dptr(out["t"]), _dptr(out["bot"]), _dptr(out["objective"]), _dptr(out["dual_obj"]),
+                _dptr(out["rel_gap"]), _dptr(out["r_pri"]), _dptr(out["r_dual"]),
+                out["iters"].ctypes.data_as(_IP), out["plan_status"].ctypes.data_as(_IP))
+    _check(library().ladmm_solve_batch(case._h, k, w, mp, C.byref(o), C.byref(r)))
+    return out
+
+
+def unpack(words, n):
+    """k x W uint64 -> k x n bool (bit b of word w = element 64 w + b)."""
+    words = np.asarray(words, np.uint64)
+    bits = (words[:, :, None] >> np.arange(64, dtype=np.uint64)) & np.uint64(1)
+    return bits.reshape(words.shape[0], -1)[:, :n].astype(bool)
+
+
+def select_ld_points(ctx: Context, volumes, n_ld, seed: int):
+    """Algorithm 1 on the device.  volumes: k x n_vox bool (or k x W uint64 with
+    n_vox given as volumes.n_vox).  Returns (P, masks) with masks k x |P| bool."""
+    vols = np.asarray(volumes)
+    k, n_vox = vols.shape
+    bits = _mask_words(vols, n_vox) if k else np.zeros((0, (n_vox + 63) // 64), np.uint64)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(n_ld, np.int32), (k,)))
+    W = (n_vox + 63) // 64
+    P = np.zeros(n_vox, np.int64)
+    nP = C.c_int64()
+    masks = np.zeros((max(k, 1), W), np.uint64)
+    _check(library().ladmm_select_ld_points(
+        ctx._h, k, n_vox, bits.ctypes.data_as(C.POINTER(C.c_uint64)), n.ctypes.data_as(_IP),
+        C.c_uint64(int(seed) & ((1 << 64) - 1)), P.ctypes.data_as(C.POINTER(C.c_int64)),
+        C.byref(nP), masks.ctypes.data_as(C.POINTER(C.c_uint64))))
+    npts = nP.value
+    return P[:npts], masks[:k], unpack(masks[:k], npts) if k else np.zeros((0, 0), bool)
