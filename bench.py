@@ -107,6 +107,7 @@ def main():
         b.iterate(ITERS_PER_STEP)     # synchronous: returns after the check is read back
     wall = time.perf_counter() - t0
     ktimes = b.kernel_times()
+    tiles = b.tiles()
     b.set_profiling(False)
     res = b.results(with_t=False)
     b.close()
@@ -161,7 +162,8 @@ def main():
                                f"{k} plans ({cases.CONFIG_PLANS[cfg]}x{cases.CONFIG_PLANS[cfg]} "
                                f"slider grid), {precision} dose block",
                    "points": N, "shots": n_t, "plans": k,
-                   "iterations_per_step": ITERS_PER_STEP, "setup_ms": round(setup_ms, 2)},
+                   "iterations_per_step": ITERS_PER_STEP, "setup_ms": round(setup_ms, 2),
+                   "tiles": {"gemm1": tiles[0], "gemm2": tiles[1]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

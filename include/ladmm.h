@@ -189,6 +189,13 @@ int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_i
  * the fused z- and y-steps), 5 objective product, 6 shot-time scaling,
  * 7 finalize.  ms_total and launches are arrays of LADMM_N_KERNEL_CLASSES. */
 #define LADMM_N_KERNEL_CLASSES 8
+/* Tile configurations chosen for the two dose-matrix products of a batch.
+ * Before its first iteration a batch times every tile configuration of the
+ * products on its own data and keeps the fastest (cached per case and padded
+ * plan count).  The configurations differ only in how the work is split, not
+ * in the order of any floating-point sum, so the choice never changes a result.
+ * Values are indices into the library's configuration tables. */
+int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2);
 int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
 int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
 

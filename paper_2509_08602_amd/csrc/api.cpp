@@ -129,6 +129,7 @@ struct ladmm_case {
   int nchunk1 = 1, nchunk2 = 1;
   int refs = 0;              // live batches
   bool destroyed = false;    // destroy requested while batches were alive
+  std::vector<std::pair<int, std::pair<int, int>>> tuned;   // kp -> (GEMM1, GEMM2) tiles
 };
 
 struct ladmm_batch {
@@ -143,7 +144,7 @@ struct ladmm_batch {
   double *invrho = nullptr, *bbot = nullptr, *wbot = nullptr;
   int32_t *active = nullptr;
   void *P1 = nullptr;
-  double *r = nullptr, *P2 = nullptr;
+  double *r = nullptr, *P2 = nullptr, *v = nullptr;
   void *vT = nullptr, *that = nullptr;
   double *admm_stats = nullptr, *post_stats = nullptr, *obj_stats = nullptr, *fin = nullptr;
   int admm_blocks = 0, post_blocks = 0, obj_blocks = 0;
@@ -159,6 +160,9 @@ struct ladmm_batch {
   double iterate_ms = 0.0;
   int64_t plan_iters = 0;
   int iters_run = 0;
+  // tile configurations of the two dose-matrix products (autotuned)
+  int cfg1 = 0, cfg2 = 0;
+  bool tuned = false;
   // per-kernel event timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -291,7 +295,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   // GEMM split factors depend on the case only, so a plan's arithmetic does
   // not depend on how many other plans share its batch.
   c->nchunk1 = std::max(1, std::min((1024 + c->ntp / 64 - 1) / (c->ntp / 64), c->Np / 256));
-  c->nchunk2 = std::max(1, std::min((512 + c->mAp / 64 - 1) / (c->mAp / 64), c->mAp / 64));
+  c->nchunk2 = std::max(1, std::min(8, (256 + c->mAp / 64 - 1) / (c->mAp / 64)));
 
   auto cleanup = [&](int rc) {
     for (void *p : c->allocs) hipFree(p);
@@ -652,14 +656,17 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk1 * c->ntp * kp * Tsz)); b->P1 = p;
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->r = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk2 * c->mAp * kp * sizeof(double))); b->P2 = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->v = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->vT = p;
   B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->that = p;
-  b->admm_blocks = c->Np / kTileRows;
-  b->obj_blocks = c->Np / kTileRows;
-  b->post_blocks = (c->mAp + c->n_sec + 31) / 32;
-  B_RC(batch_alloc(b, &p, (size_t)b->admm_blocks * kAdmmStats * kp * sizeof(double))); b->admm_stats = (double *)p;
+  // statistics partials: one per row block of GEMM2, sized for the smallest
+  // row block of any tile configuration (the autotuner may pick it)
+  const int max_row_blocks = c->Np / kNnMinRows;
+  b->admm_blocks = b->obj_blocks = c->Np / gemm_nn_block_rows(b->cfg2, c->Np, kp);
+  b->post_blocks = post_blocks(c->L);
+  B_RC(batch_alloc(b, &p, (size_t)max_row_blocks * kAdmmStats * kp * sizeof(double))); b->admm_stats = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)b->post_blocks * kAdmmStats * kp * sizeof(double))); b->post_stats = (double *)p;
-  B_RC(batch_alloc(b, &p, (size_t)b->obj_blocks * kObjStats * kp * sizeof(double))); b->obj_stats = (double *)p;
+  B_RC(batch_alloc(b, &p, (size_t)max_row_blocks * kObjStats * kp * sizeof(double))); b->obj_stats = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)kp * kFinal * sizeof(double))); b->fin = (double *)p;
   B_HIP(hipHostMalloc((void **)&b->h_fin, (size_t)kp * kFinal * sizeof(double), hipHostMallocDefault));
   B_HIP(hipMemsetAsync(b->q, 0, (size_t)c->Np * kp * Tsz, b->stream));
@@ -717,12 +724,12 @@ int iterate_once(ladmm_batch *b, bool stats) {
   PointTable<T> pt = point_table<T>(b);
   SmallArgs sa = small_args(b);
   PROF(0, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->q, kp, (T *)b->P1, kp, c->ntp,
-                      kp, c->Np, c->nchunk1, &pt)));
+                      kp, c->Np, c->nchunk1, &pt, b->cfg1)));
   PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
   PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
                            c->nchunk2, nullptr)));
-  PROF(3, (post<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->qs, b->q2, (T *)b->vT,
-                   stats ? b->post_stats : nullptr, &b->post_blocks)));
+  PROF(3, (vreduce<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (T *)b->vT)));
+  PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
   EpiArgs<T> ea{};
   ea.q = (T *)b->q;
   ea.ldq = kp;
@@ -732,13 +739,13 @@ int iterate_once(ladmm_batch *b, bool stats) {
   ea.nstat_cols = kp;
   ea.pt = pt;
   PROF(4, (gemm_nn<T>(s, stats ? EPI_ADMM_STATS : EPI_ADMM, (const T *)c->D, c->ntp,
-                      (const T *)b->vT, kp, c->Np, kp, c->ntp, ea)));
+                      (const T *)b->vT, kp, c->Np, kp, c->ntp, ea, b->cfg2)));
   if (stats) {
     PROF(6, (shot_scaled<T>(s, sa, b->q2, (T *)b->that)));
     EpiArgs<T> eo = ea;
     eo.stats = b->obj_stats;
     PROF(5, (gemm_nn<T>(s, EPI_OBJ, (const T *)c->D, c->ntp, (const T *)b->that, kp, c->Np, kp,
-                        c->ntp, eo)));
+                        c->ntp, eo, b->cfg2)));
     FinalArgs fa;
     fa.admm_stats = b->admm_stats;
     fa.admm_blocks = b->admm_blocks;
@@ -763,10 +770,79 @@ int iterate_any(ladmm_batch *b, bool stats) {
   return b->c->precision == LADMM_F64 ? iterate_once<double>(b, stats) : iterate_once<float>(b, stats);
 }
 
+// Number of GEMM2 row blocks (statistics partials) for the chosen configuration.
+void set_row_blocks(ladmm_batch *b) {
+  const int rows = gemm_nn_block_rows(b->cfg2, b->c->Np, b->kp);
+  b->admm_blocks = b->obj_blocks = b->c->Np / rows;
+}
+
+// Pick the fastest tile configuration of each dose-matrix product for this
+// case and plan count: a few timed launches of every valid configuration on the
+// live batch (GEMM2 runs with its writes masked off).  Results are cached per
+// case and padded plan count.  The configurations change only the work split,
+// never the order of the sums, so the choice does not affect the iterates.
+template <typename T>
+int autotune(ladmm_batch *b) {
+  ladmm_case *c = b->c;
+  for (auto &e : c->tuned)
+    if (e.first == b->kp) {
+      b->cfg1 = e.second.first;
+      b->cfg2 = e.second.second;
+      b->tuned = true;
+      set_row_blocks(b);
+      return LADMM_OK;
+    }
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  PointTable<T> pt = point_table<T>(b);
+  int32_t *noact = nullptr;
+  HIPC(hipMalloc((void **)&noact, kp * sizeof(int32_t)));
+  hipError_t e = hipMemsetAsync(noact, 0, kp * sizeof(int32_t), s);
+  EpiArgs<T> ea{};
+  ea.q = (T *)b->q;
+  ea.ldq = kp;
+  ea.invrho = b->invrho;
+  ea.active = noact;
+  ea.pt = pt;
+  float best1 = 1e30f, best2 = 1e30f;
+  for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
+    for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+      const bool ok = which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, kp) : gemm_nn_cfg_ok(cfg, c->Np, kp);
+      if (!ok) continue;
+      float tot = 0.f;
+      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(b->ev0, s);
+        if (e == hipSuccess)
+          e = which == 0 ? gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->q, kp, (T *)b->P1,
+                                      kp, c->ntp, kp, c->Np, c->nchunk1, &pt, cfg)
+                         : gemm_nn<T>(s, EPI_ADMM, (const T *)c->D, c->ntp, (const T *)b->vT, kp,
+                                      c->Np, kp, c->ntp, ea, cfg);
+        if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+        if (rep > 0) tot += ms;     // the first launch warms caches
+      }
+      if (which == 0 && tot < best1) { best1 = tot; b->cfg1 = cfg; }
+      if (which == 1 && tot < best2) { best2 = tot; b->cfg2 = cfg; }
+    }
+  }
+  hipFree(noact);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  c->tuned.push_back({kp, {b->cfg1, b->cfg2}});
+  b->tuned = true;
+  set_row_blocks(b);
+  return LADMM_OK;
+}
+
 // Run n iterations (the last one with statistics), update the host records and,
 // if `decide`, freeze plans that meet the stopping test.
 int run_chunk(ladmm_batch *b, int n, bool decide) {
   if (n <= 0) return LADMM_OK;
+  if (!b->tuned) {
+    int rc = b->c->precision == LADMM_F64 ? autotune<double>(b) : autotune<float>(b);
+    if (rc) return rc;
+  }
   int n_active = 0;
   for (int j = 0; j < b->k; ++j) n_active += b->h_active[j] != 0;
   HIPC(hipEventRecord(b->ev0, b->stream));
@@ -1085,6 +1161,13 @@ int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *la
     if (ms_total) ms_total[i] = b->kms[i];
     if (launches) launches[i] = b->kcount[i];
   }
+  return LADMM_OK;
+}
+
+int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (gemm1) *gemm1 = b->cfg1;
+  if (gemm2) *gemm2 = b->cfg2;
   return LADMM_OK;
 }
 

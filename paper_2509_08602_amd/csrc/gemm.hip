@@ -3,15 +3,23 @@
 // form that follows it), with the elementwise steps of Eq. (admm) fused into
 // their prologue and epilogue, plus the FP64 products of the case setup.
 //
-// Both kernels stage BK-deep slices of the operands through LDS and feed
-// v_mfma_*_16x16x4 instructions (f32 or f64).  A 256-thread workgroup holds a
-// BM x BN output tile as 2 x 2 wavefronts; each wavefront owns
-// (BM/32) x (BN/32) 16x16 accumulator tiles.
+// Shapes.  The dose block D^ is tall (N points x n_t shots, N up to 2e5) and
+// the plan dimension is short (k <= a few hundred), so a workgroup takes a slab
+// of D^ and multiplies it by a whole block of plan columns (BN up to 128): D^ is
+// streamed from HBM once per product.  BK-deep slices of both operands are
+// staged through double-buffered LDS with 16-byte global loads; the next slice
+// is fetched into registers while the current one feeds the MFMA pipes.
+// Four wavefronts per workgroup, arranged WM x WN over the output tile, each
+// own TM x TN tiles of 16 x 16.
 //
 // MFMA 16x16x4 operand layout (gfx950, checked by a lane probe): lane l supplies
 // A[i][k] with i = l % 16, k = l / 16 and B[k][j] with j = l % 16, k = l / 16.
 // It receives D[i][j] for j = l % 16 and, in accumulator register r = 0..3,
 // i = 4 (l / 16) + r for the f32 instruction but i = l / 16 + 4 r for f64.
+//
+// LDS padding: a half-wavefront (32 lanes) reads 16 consecutive words from
+// two rows; a row stride congruent to 16 (mod 32) words keeps the 32 banks
+// distinct (rows of k-contiguous tiles use a stride congruent to 2 instead).
 #include "kernels.h"
 
 #include <math.h>
@@ -32,6 +40,25 @@ __device__ __forceinline__ d4v mfma16(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Row of the 16x16 output tile held by `lane` in accumulator register r.
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+
+// 16-byte vector of T.
+template <typename T> struct V16;
+template <> struct V16<float> { typedef float4 V; static constexpr int n = 4; };
+template <> struct V16<double> { typedef double2 V; static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename V16<T>::V &v, int i);
+template <> __device__ __forceinline__ float vget<float>(const float4 &v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+template <> __device__ __forceinline__ double vget<double>(const double2 &v, int i) {
+  return i == 0 ? v.x : v.y;
+}
+
 // Upper bound u of dose point p in plan j (App. A: w/N per group, +inf for OAR;
 // 0 for a low-dose point outside the plan's second-pass subset).
 template <typename T>
@@ -47,24 +74,27 @@ __device__ __forceinline__ T upper_of(const PointTable<T> &pt, int g, int p, int
 template <typename T>
 __device__ __forceinline__ T clip0u(T q, T u) { return fmin(fmax(q, T(0)), u); }
 
-// Row of the 16x16 output tile held by `lane` in accumulator register r.
-template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
-template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
-template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
-
 // ---------------------------------------------------------------------------
-// P[z][m][n] = sum_{k in chunk z} A[k][m] * B'[k][n]
+// P[z][m][n] = sum_{k in chunk z} A[k][m] * B'[k][n],  A: K x M, B: K x N
+// B' = B, or with the ADMM prologue B' = 2 clip(q, 0, u) - q  (z1 - y1).
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK, bool PRO>
-__global__ __launch_bounds__(256) void k_gemm_tn(const T *__restrict__ A, int lda,
-                                                 const T *__restrict__ B, int ldb,
-                                                 T *__restrict__ P, int ldp, size_t pstride,
-                                                 int K, int kchunk, PointTable<T> pt) {
-  constexpr int TM = BM / 32, TN = BN / 32;
-  __shared__ T sA[BK][BM + 1];
-  __shared__ T sB[BK][BN + 1];
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool PRO>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(const T *__restrict__ A, int lda,
+                                                          const T *__restrict__ B, int ldb,
+                                                          T *__restrict__ P, int ldp, size_t pstride,
+                                                          int K, int kchunk, PointTable<T> pt) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int VN = V16<T>::n;
+  constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
+  static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
+  constexpr int PADA = (sizeof(T) == 4) ? 16 : 8, PADB = PADA;
+  constexpr int AV = BK * BM / VN, BV = BK * BN / VN;           // vectors per slice
+  constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;  // per thread
+  typedef typename V16<T>::V VT;
+  __shared__ T sA[2][BK][BM + PADA];
+  __shared__ T sB[2][BK][BN + PADB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
@@ -74,40 +104,83 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T *__restrict__ A, int ld
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = typename MV<T>::V{0, 0, 0, 0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    for (int e = tid; e < BK * BM; e += 256) {
-      const int kk = e / BM, mm = e % BM, k = k0 + kk;
-      sA[kk][mm] = (k < kend) ? A[(size_t)k * lda + m0 + mm] : T(0);
-    }
-    for (int e = tid; e < BK * BN; e += 256) {
-      const int kk = e / BN, nn = e % BN, k = k0 + kk;
-      T val = T(0);
-      if (k < kend) {
-        const T qv = B[(size_t)k * ldb + n0 + nn];
-        if (PRO) {
-          const int g = pt.grp[k];
-          const T z = clip0u(qv, upper_of(pt, g, k, n0 + nn));
-          val = T(2) * z - qv;               // z1 - y1 with y1 = q - z1
-        } else {
-          val = qv;
-        }
+  VT ra[AVT], rb[BVT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        const int kk = e / (BM / VN), mm = (e % (BM / VN)) * VN, k = k0 + kk;
+        ra[i] = (k < kend) ? *reinterpret_cast<const VT *>(A + (size_t)k * lda + m0 + mm) : VT{};
       }
-      sB[kk][nn] = val;
     }
-    __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T a[TM], b[TN];
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int kk = e / (BN / VN), nn = (e % (BN / VN)) * VN, k = k0 + kk;
+        VT v = VT{};
+        if (k < kend) {
+          v = *reinterpret_cast<const VT *>(B + (size_t)k * ldb + n0 + nn);
+          if (PRO) {
+            const int g = pt.grp[k];
+            T *pv = reinterpret_cast<T *>(&v);
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm) a[tm] = sA[kk + (lane >> 4)][wm * TM * 16 + tm * 16 + (lane & 15)];
-#pragma unroll
-      for (int tn = 0; tn < TN; ++tn) b[tn] = sB[kk + (lane >> 4)][wn * TN * 16 + tn * 16 + (lane & 15)];
-#pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma16(a[tm], b[tn], acc[tm][tn]);
+            for (int c = 0; c < VN; ++c) {
+              const T z = clip0u(pv[c], upper_of(pt, g, k, n0 + nn + c));
+              pv[c] = T(2) * z - pv[c];
+            }
+          }
+        }
+        rb[i] = v;
+      }
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        const int kk = e / (BM / VN), mm = (e % (BM / VN)) * VN;
+        *reinterpret_cast<VT *>(&sA[buf][kk][mm]) = ra[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int kk = e / (BN / VN), nn = (e % (BN / VN)) * VN;
+        *reinterpret_cast<VT *>(&sB[buf][kk][nn]) = rb[i];
+      }
+    }
+  };
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
     __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) load(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T a[TM], b[TN];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+          a[tm] = sA[buf][kk + (lane >> 4)][wm * TM * 16 + tm * 16 + (lane & 15)];
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+          b[tn] = sB[buf][kk + (lane >> 4)][wn * TN * 16 + tn * 16 + (lane & 15)];
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma16(a[tm], b[tn], acc[tm][tn]);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
   T *Pz = P + (size_t)blockIdx.z * pstride;
 #pragma unroll
@@ -122,50 +195,96 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const T *__restrict__ A, int ld
       }
 }
 
+// Column block of the plan dimension: the whole of N when it is at most 128.
+static int pick_bn(int N) {
+  if (N <= 128 && N % 32 == 0) return N;
+  if (N % 128 == 0) return 128;
+  if (N % 64 == 0) return 64;
+  return 32;
+}
+
+// Tile configurations of the split-K product (row tile BM, wavefront grid WM x WN).
+struct TnCfg { int bm, wm, wn; };
+static const TnCfg kTnCfgs[kGemmCfgs] = {{64, 2, 2}, {32, 2, 2}, {64, 4, 2}, {64, 4, 1}};
+
+bool gemm_tn_cfg_ok(int cfg, int M, int N) {
+  if (cfg < 0 || cfg >= kGemmCfgs) return false;
+  const TnCfg c = kTnCfgs[cfg];
+  const int BN = pick_bn(N);
+  return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
+}
+
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
-                   int M, int N, int K, int nchunk, const PointTable<T> *pro) {
-  constexpr int BM = 64, BK = 16;
-  if (M % BM != 0 || N % 32 != 0 || nchunk < 1) return hipErrorInvalidValue;
+                   int M, int N, int K, int nchunk, const PointTable<T> *pro, int cfg) {
+  constexpr int BK = 16;
+  if (!gemm_tn_cfg_ok(cfg, M, N)) cfg = 0;
+  if (!gemm_tn_cfg_ok(cfg, M, N) || N % 32 != 0 || nchunk < 1) return hipErrorInvalidValue;
+  if (lda % V16<T>::n || ldb % V16<T>::n) return hipErrorInvalidValue;
   int kchunk = (K + nchunk - 1) / nchunk;
   kchunk = (kchunk + BK - 1) / BK * BK;
   const size_t pstride = (size_t)M * ldp;
   PointTable<T> pt{};
   if (pro) pt = *pro;
-  if (N % 64 == 0) {
-    dim3 grid(M / BM, N / 64, nchunk);
-    if (pro)
-      hipLaunchKernelGGL((k_gemm_tn<T, BM, 64, BK, true>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                         P, ldp, pstride, K, kchunk, pt);
-    else
-      hipLaunchKernelGGL((k_gemm_tn<T, BM, 64, BK, false>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                         P, ldp, pstride, K, kchunk, pt);
-  } else {
-    dim3 grid(M / BM, N / 32, nchunk);
-    if (pro)
-      hipLaunchKernelGGL((k_gemm_tn<T, BM, 32, BK, true>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                         P, ldp, pstride, K, kchunk, pt);
-    else
-      hipLaunchKernelGGL((k_gemm_tn<T, BM, 32, BK, false>), grid, dim3(256), 0, s, A, lda, B, ldb,
-                         P, ldp, pstride, K, kchunk, pt);
+  const int BN = pick_bn(N);
+  const TnCfg c = kTnCfgs[cfg];
+  dim3 grid(M / c.bm, N / BN, nchunk);
+#define TN_ONE(BMv, BNv, WMv, WNv)                                                            \
+  do {                                                                                       \
+    if (pro)                                                                                 \
+      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BK, WMv, WNv, true>), grid, dim3(64 * WMv * WNv), \
+                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BK, WMv, WNv, false>), grid, dim3(64 * WMv * WNv), \
+                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
+  } while (0)
+#define TN_BN(BMv, WMv, WNv)                                  \
+  switch (BN) {                                               \
+    case 32: if (32 % (16 * WNv) == 0) TN_ONE(BMv, 32, WMv, WNv); break; \
+    case 64: TN_ONE(BMv, 64, WMv, WNv); break;                \
+    case 96: if (96 % (16 * WNv) == 0) TN_ONE(BMv, 96, WMv, WNv); break; \
+    case 128: TN_ONE(BMv, 128, WMv, WNv); break;              \
+    default: return hipErrorInvalidValue;                     \
   }
+  switch (cfg) {
+    case 0: TN_BN(64, 2, 2) break;
+    case 1: TN_BN(32, 2, 2) break;
+    case 2: TN_BN(64, 4, 2) break;
+    case 3: TN_BN(64, 4, 1) break;
+  }
+#undef TN_BN
+#undef TN_ONE
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // C = A B with fused epilogues (A: M x K row-major, B: K x N row-major)
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int lda,
-                                                 const T *__restrict__ B, int ldb, int K,
-                                                 EpiArgs<T> ea) {
-  constexpr int TM = BM / 32, TN = BN / 32;
-  __shared__ T sA[BM][BK + 1];
-  __shared__ T sB[BK][BN + 1];
+template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ A, int lda,
+                                                          const T *__restrict__ B, int ldb, int K,
+                                                          EpiArgs<T> ea) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int VN = V16<T>::n;
+  constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
+  static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
+  constexpr int PADA = (sizeof(T) == 4) ? 2 : 1;       // k-contiguous rows: stride = 2 mod 32 words
+  constexpr int PADB = (sizeof(T) == 4) ? 16 : 8;
+  constexpr int AV = BM * BK / VN, BV = BK * BN / VN;
+  constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;
   constexpr int NST = (EPI == EPI_OBJ) ? kObjStats : kAdmmStats;
-  __shared__ double sred[2][NST][BN];
+  typedef typename V16<T>::V VT;
+  // operand tiles; the statistics reduction reuses the same LDS after the K loop
+  constexpr size_t kBytesA = sizeof(T) * 2 * BM * (BK + PADA);
+  constexpr size_t kBytesB = sizeof(T) * 2 * BK * (BN + PADB);
+  constexpr size_t kBytesR = sizeof(double) * WM * NST * BN;
+  constexpr size_t kBytes = (kBytesA + kBytesB > kBytesR) ? kBytesA + kBytesB : kBytesR;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  auto sA = reinterpret_cast<T (*)[BM][BK + PADA]>(smem);
+  auto sB = reinterpret_cast<T (*)[BK][BN + PADB]>(smem + kBytesA);
+  auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   typename MV<T>::V acc[TM][TN];
 #pragma unroll
@@ -173,29 +292,70 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = typename MV<T>::V{0, 0, 0, 0};
 
+  VT ra[AVT], rb[BVT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        const int mm = e / (BK / VN), kk = (e % (BK / VN)) * VN;
+        ra[i] = *reinterpret_cast<const VT *>(A + (size_t)(m0 + mm) * lda + k0 + kk);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int kk = e / (BN / VN), nn = (e % (BN / VN)) * VN;
+        rb[i] = *reinterpret_cast<const VT *>(B + (size_t)(k0 + kk) * ldb + n0 + nn);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        const int mm = e / (BK / VN), kk = (e % (BK / VN)) * VN;
+        const T *pv = reinterpret_cast<const T *>(&ra[i]);
+#pragma unroll
+        for (int c = 0; c < VN; ++c) sA[buf][mm][kk + c] = pv[c];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int kk = e / (BN / VN), nn = (e % (BN / VN)) * VN;
+        *reinterpret_cast<VT *>(&sB[buf][kk][nn]) = rb[i];
+      }
+    }
+  };
+
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int mm = e / BK, kk = e % BK;
-      sA[mm][kk] = A[(size_t)(m0 + mm) * lda + k0 + kk];
-    }
-    for (int e = tid; e < BK * BN; e += 256) {
-      const int kk = e / BN, nn = e % BN;
-      sB[kk][nn] = B[(size_t)(k0 + kk) * ldb + n0 + nn];
-    }
-    __syncthreads();
+    const bool more = k0 + BK < K;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[TM], b[TN];
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm) a[tm] = sA[wm * TM * 16 + tm * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int tm = 0; tm < TM; ++tm)
+        a[tm] = sA[buf][wm * TM * 16 + tm * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int tn = 0; tn < TN; ++tn) b[tn] = sB[kk + (lane >> 4)][wn * TN * 16 + tn * 16 + (lane & 15)];
+      for (int tn = 0; tn < TN; ++tn)
+        b[tn] = sB[buf][kk + (lane >> 4)][wn * TN * 16 + tn * 16 + (lane & 15)];
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma16(a[tm], b[tn], acc[tm][tn]);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   if (EPI == EPI_STORE) {
@@ -220,17 +380,15 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
     for (int q = 0; q < NST; ++q) st[tn][q] = 0.0;
 
 #pragma unroll
-  for (int tn = 0; tn < TN; ++tn) {
-    const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
-    const double invrho = ea.invrho[n];
-    const bool act = ea.active[n] != 0;
+  for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm)
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * TM * 16 + tm * 16 + acc_row<T>(lane, r);
+      const int g = ea.pt.grp[m];
+      const T sg = ea.pt.sig[m];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * TM * 16 + tm * 16 + acc_row<T>(lane, r);
-        const int g = ea.pt.grp[m];
-        const T sg = ea.pt.sig[m];
+      for (int tn = 0; tn < TN; ++tn) {
+        const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
         const T u = upper_of(ea.pt, g, m, n);
         const T s = acc[tm][tn][r];
         if (EPI == EPI_OBJ) {
@@ -246,8 +404,8 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
           const T qv = *qp;
           const T z = clip0u(qv, u);
           // q' = x1 + y1 = z1 - c/rho - A_s' v, with c_p = -sign_p
-          const T qn = z + sg * (T)invrho - s;
-          if (act) *qp = qn;
+          const T qn = z + sg * (T)ea.invrho[n] - s;
+          if (ea.active[n]) *qp = qn;
           if (EPI == EPI_ADMM_STATS) {
             const double yo = (double)qv - (double)z;
             const double zn = (double)clip0u(qn, u);
@@ -262,7 +420,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
           }
         }
       }
-  }
+    }
   if (EPI == EPI_ADMM) return;
 
   // reduce over lanes with the same column (l, l+16, l+32, l+48), then waves
@@ -281,47 +439,79 @@ __global__ __launch_bounds__(256) void k_gemm_nn(const T *__restrict__ A, int ld
       if (lane < 16) sred[wm][q][wn * TN * 16 + tn * 16 + lane] = v;
     }
   __syncthreads();
-  for (int e = tid; e < NST * BN; e += 256) {
+  for (int e = tid; e < NST * BN; e += NT) {
     const int q = e / BN, c = e % BN;
-    const double a = sred[0][q][c], b = sred[1][q][c];
-    const double v = (EPI == EPI_OBJ && q == 1) ? fmax(a, b) : a + b;
+    double v = sred[0][q][c];
+#pragma unroll
+    for (int w = 1; w < WM; ++w) v = (EPI == EPI_OBJ && q == 1) ? fmax(v, sred[w][q][c]) : v + sred[w][q][c];
     ea.stats[((size_t)blockIdx.x * NST + q) * ea.nstat_cols + n0 + c] = v;
   }
 }
 
+// Tile configurations of the point-row product (BM rows, wavefront grid WM x WN).
+struct NnCfg { int bm, wm, wn; };
+static const NnCfg kNnCfgs[kGemmCfgs] = {{128, 4, 1}, {64, 2, 2}, {128, 4, 2}, {64, 4, 2}};
+
+int gemm_nn_block_rows(int cfg, int M, int N) {
+  if (!gemm_nn_cfg_ok(cfg, M, N)) cfg = 0;
+  return kNnCfgs[cfg].bm;
+}
+
+bool gemm_nn_cfg_ok(int cfg, int M, int N) {
+  if (cfg < 0 || cfg >= kGemmCfgs) return false;
+  const NnCfg c = kNnCfgs[cfg];
+  const int BN = pick_bn(N);
+  return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
+}
+
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb, int M,
-                   int N, int K, const EpiArgs<T> &ea) {
-  constexpr int BM = 64, BK = 16;
-  if (M % BM != 0 || N % 32 != 0 || K % BK != 0) return hipErrorInvalidValue;
-#define LAUNCH_NN(BN, E)                                                                  \
-  hipLaunchKernelGGL((k_gemm_nn<T, BM, BN, BK, E>), dim3(M / BM, N / BN), dim3(256), 0, s, A, \
-                     lda, B, ldb, K, ea)
-#define LAUNCH_NN_E(BN)                                   \
-  switch (epi) {                                          \
-    case EPI_STORE: LAUNCH_NN(BN, EPI_STORE); break;      \
-    case EPI_ADMM: LAUNCH_NN(BN, EPI_ADMM); break;        \
-    case EPI_ADMM_STATS: LAUNCH_NN(BN, EPI_ADMM_STATS); break; \
-    case EPI_OBJ: LAUNCH_NN(BN, EPI_OBJ); break;          \
-    default: return hipErrorInvalidValue;                 \
+                   int N, int K, const EpiArgs<T> &ea, int cfg) {
+  constexpr int BK = 16;
+  if (!gemm_nn_cfg_ok(cfg, M, N)) cfg = 0;
+  if (!gemm_nn_cfg_ok(cfg, M, N) || N % 32 != 0 || K % BK != 0) return hipErrorInvalidValue;
+  if (lda % V16<T>::n || ldb % V16<T>::n) return hipErrorInvalidValue;
+  const int BN = pick_bn(N);
+  const NnCfg c = kNnCfgs[cfg];
+  const dim3 grid(M / c.bm, N / BN);
+#define NN_ONE(BMv, BNv, WMv, WNv, E)                                                          \
+  hipLaunchKernelGGL((k_gemm_nn<T, BMv, BNv, BK, WMv, WNv, E>), grid, dim3(64 * WMv * WNv), 0, s, \
+                     A, lda, B, ldb, K, ea)
+#define NN_E(BMv, BNv, WMv, WNv)                                          \
+  switch (epi) {                                                         \
+    case EPI_STORE: NN_ONE(BMv, BNv, WMv, WNv, EPI_STORE); break;        \
+    case EPI_ADMM: NN_ONE(BMv, BNv, WMv, WNv, EPI_ADMM); break;          \
+    case EPI_ADMM_STATS: NN_ONE(BMv, BNv, WMv, WNv, EPI_ADMM_STATS); break; \
+    case EPI_OBJ: NN_ONE(BMv, BNv, WMv, WNv, EPI_OBJ); break;            \
+    default: return hipErrorInvalidValue;                                \
   }
-  if (N % 64 == 0) {
-    LAUNCH_NN_E(64)
-  } else {
-    LAUNCH_NN_E(32)
+#define NN_BN(BMv, WMv, WNv)                                              \
+  switch (BN) {                                                          \
+    case 32: if (32 % (16 * WNv) == 0) { NN_E(BMv, 32, WMv, WNv) } break; \
+    case 64: { NN_E(BMv, 64, WMv, WNv) } break;                          \
+    case 96: if (96 % (16 * WNv) == 0) { NN_E(BMv, 96, WMv, WNv) } break; \
+    case 128: { NN_E(BMv, 128, WMv, WNv) } break;                        \
+    default: return hipErrorInvalidValue;                                \
   }
-#undef LAUNCH_NN_E
-#undef LAUNCH_NN
+  switch (cfg) {
+    case 0: NN_BN(128, 4, 1) break;
+    case 1: NN_BN(64, 2, 2) break;
+    case 2: NN_BN(128, 4, 2) break;
+    case 3: NN_BN(64, 4, 2) break;
+  }
+#undef NN_BN
+#undef NN_E
+#undef NN_ONE
   return hipGetLastError();
 }
 
 template hipError_t gemm_tn<float>(hipStream_t, const float *, int, const float *, int, float *,
-                                   int, int, int, int, int, const PointTable<float> *);
+                                   int, int, int, int, int, const PointTable<float> *, int);
 template hipError_t gemm_tn<double>(hipStream_t, const double *, int, const double *, int,
-                                    double *, int, int, int, int, int, const PointTable<double> *);
+                                    double *, int, int, int, int, int, const PointTable<double> *, int);
 template hipError_t gemm_nn<float>(hipStream_t, int, const float *, int, const float *, int, int,
-                                   int, int, const EpiArgs<float> &);
+                                   int, int, const EpiArgs<float> &, int);
 template hipError_t gemm_nn<double>(hipStream_t, int, const double *, int, const double *, int,
-                                    int, int, int, const EpiArgs<double> &);
+                                    int, int, int, const EpiArgs<double> &, int);
 
 }  // namespace ladmm

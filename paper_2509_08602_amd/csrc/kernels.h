@@ -6,7 +6,7 @@
 namespace ladmm {
 
 // Tile sizes shared by the launchers and the host-side padding rules.
-constexpr int kTileRows = 64;     // rows (points, shots) of a GEMM tile
+constexpr int kTileRows = 128;    // dose-point rows of a GEMM2 tile (point padding)
 constexpr int kSmallAlign = 64;   // padding of the shot / small-row dimension
 
 // Layout of the small (m_A) vectors: shot rows t in [0, ntp) (t < n_t real),
@@ -31,9 +31,19 @@ struct PointTable {
 // ---- generic products -----------------------------------------------------
 // P[z][m][n] = sum over rows k of chunk z of A[k][m] * B[k][n]   (A: K x M, B: K x N)
 // With the ADMM prologue, B is replaced by W = 2 clip(q, 0, u) - q.
+// Tile configuration cfg in [0, kGemmCfgs) (0 is valid for every padded shape;
+// an invalid cfg falls back to 0).  The configurations do not change the
+// order of the floating-point sums, only the work split.
+constexpr int kGemmCfgs = 4;
+bool gemm_tn_cfg_ok(int cfg, int M, int N);
+bool gemm_nn_cfg_ok(int cfg, int M, int N);
+// Rows per workgroup of the point-row product in configuration cfg: the
+// statistics epilogues write one partial per workgroup row block, M / rows.
+int gemm_nn_block_rows(int cfg, int M, int N);
+constexpr int kNnMinRows = 64;   // smallest row block of any configuration
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
-                   int M, int N, int K, int nchunk, const PointTable<T> *pro);
+                   int M, int N, int K, int nchunk, const PointTable<T> *pro, int cfg = 0);
 // P[z][m][n] for FP64 accumulation of FP64 operands is the T = double case.
 
 // Epilogues of C = A B (A: M x K row-major, B: K x N row-major).
@@ -51,7 +61,7 @@ struct EpiArgs {
 };
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb,
-                   int M, int N, int K, const EpiArgs<T> &ea);
+                   int M, int N, int K, const EpiArgs<T> &ea, int cfg = 0);
 
 // ---- setup ------------------------------------------------------------------
 // Dt[p][t] = sig[p] * phi[p][t] / thr[p]; zero padding rows/cols (FP64).
@@ -88,11 +98,15 @@ struct SmallArgs {
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
                const double *qs, const double *q2, double *r);
-// v = sum of Sinv*r partials; q2 <- v + Pi(q2); qs <- max(qs,0) - (A_sec' v);
-// vT <- (T) v_top; optional stats partials [block][kAdmmStats][kp].
+// v = sum of the Sinv r partials (mAp x kp) and vT = (T) v_top (ntp x kp).
 template <typename T>
-hipError_t post(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                double *qs, double *q2, T *vT, double *stats, int *nblocks_out);
+hipError_t vreduce(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
+                   double *v, T *vT);
+// q2 <- v + Pi(q2); qs <- max(qs,0) - (A_sec' v); optional stats partials
+// [block][kAdmmStats][kp].
+hipError_t post(hipStream_t s, const SmallArgs &a, const double *v, double *qs, double *q2,
+                double *stats, int *nblocks_out);
+int post_blocks(const SmallLayout &L);
 // that = rho * max(q2_top, 0) (shot times over E), as T.
 template <typename T>
 hipError_t shot_scaled(hipStream_t s, const SmallArgs &a, const double *q2, T *that);

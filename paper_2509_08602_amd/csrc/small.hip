@@ -365,19 +365,33 @@ hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, i
 template hipError_t rhs<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, const double *, const double *, double *);
 template hipError_t rhs<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, const double *, const double *, double *);
 
-__device__ __forceinline__ double sum_partials(const double *P2, size_t zstride, int nchunk,
-                                               int row, int kp, int j) {
-  double v = 0.0;
-  for (int z = 0; z < nchunk; ++z) v += P2[z * zstride + (size_t)row * kp + j];
-  return v;
+template <typename T>
+__global__ void k_vreduce(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,
+                          double *__restrict__ v, T *__restrict__ vT) {
+  const int j = blockIdx.y * 64 + threadIdx.x;
+  const int m = blockIdx.x * 4 + threadIdx.y;
+  if (m >= a.L.mAp || j >= a.kp) return;
+  const size_t idx = (size_t)m * a.kp + j;
+  double acc = 0.0;
+  for (int z = 0; z < nchunk; ++z) acc += P2[z * zstride + idx];
+  v[idx] = acc;
+  if (m < a.L.ntp) vT[idx] = (T)acc;
 }
 
-constexpr int kPostRows = 32;   // rows per block of the post kernel
-
 template <typename T>
-__global__ void k_post(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,
-                       double *__restrict__ qs, double *__restrict__ q2, T *__restrict__ vT,
-                       double *__restrict__ stats) {
+hipError_t vreduce(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
+                   double *v, T *vT) {
+  hipLaunchKernelGGL((k_vreduce<T>), dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s,
+                     a, P2, zstride, nchunk, v, vT);
+  return hipGetLastError();
+}
+template hipError_t vreduce<float>(hipStream_t, const SmallArgs &, const double *, size_t, int, double *, float *);
+template hipError_t vreduce<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, double *, double *);
+
+constexpr int kPostRows = 8;   // rows per block of the post kernel (2 per thread row)
+
+__global__ void k_post(SmallArgs a, const double *__restrict__ v, double *__restrict__ qs,
+                       double *__restrict__ q2, double *__restrict__ stats) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const SmallLayout &L = a.L;
   const int kp = a.kp;
@@ -389,17 +403,15 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ P2, size_t zstrid
     const int m = blockIdx.x * kPostRows + rr;
     if (m >= total) break;
     double qv, z, qn, bnd;
-    bool sector = m >= L.mAp;
+    const bool sector = m >= L.mAp;
     if (!sector) {
       const bool top = m < L.n_t;
       const bool bot = m >= L.ntp && m < L.ntp + L.n_iso;
-      const double v = sum_partials(P2, zstride, nchunk, m, kp, j);
-      if (m < L.ntp) vT[(size_t)m * kp + j] = (T)v;
       if (!top && !bot) continue;
       bnd = top ? 0.0 : a.bbot[(size_t)(m - L.ntp) * kp + j];
       qv = q2[(size_t)m * kp + j];
       z = fmin(qv, bnd);
-      qn = v + z;                                           // x2 + y2 = v + z2
+      qn = v[(size_t)m * kp + j] + z;                        // x2 + y2 = v + z2
       if (act) q2[(size_t)m * kp + j] = qn;
     } else {
       const int sec = m - L.mAp;
@@ -407,10 +419,10 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ P2, size_t zstrid
       double atv = 0.0;                                      // (A_s' v) at this sector
       for (int c = 0; c < L.C; ++c) {
         const int t = sec * L.C + c;
-        atv -= a.beta * a.E[t] * a.cs * sum_partials(P2, zstride, nchunk, t, kp, j);
+        atv -= a.beta * a.E[t] * a.cs * v[(size_t)t * kp + j];
       }
       const int mb = L.ntp + i;
-      atv += a.beta * a.E[mb] * sum_partials(P2, zstride, nchunk, mb, kp, j);
+      atv += a.beta * a.E[mb] * v[(size_t)mb * kp + j];
       qv = qs[(size_t)sec * kp + j];
       z = fmax(qv, 0.0);
       qn = z - atv;                                          // c = 0, u = +inf here
@@ -435,25 +447,22 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ P2, size_t zstrid
   __syncthreads();
   if (threadIdx.y == 0 && valid) {
     for (int q = 0; q < kAdmmStats; ++q) {
-      const double v = red[0][q][threadIdx.x] + red[1][q][threadIdx.x] + red[2][q][threadIdx.x] +
+      const double s = red[0][q][threadIdx.x] + red[1][q][threadIdx.x] + red[2][q][threadIdx.x] +
                        red[3][q][threadIdx.x];
-      stats[((size_t)blockIdx.x * kAdmmStats + q) * kp + j] = v;
+      stats[((size_t)blockIdx.x * kAdmmStats + q) * kp + j] = s;
     }
   }
 }
 
-template <typename T>
-hipError_t post(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                double *qs, double *q2, T *vT, double *stats, int *nblocks_out) {
-  const int total = a.L.mAp + a.L.n_sec;
-  const int nb = (total + kPostRows - 1) / kPostRows;
+int post_blocks(const SmallLayout &L) { return (L.mAp + L.n_sec + kPostRows - 1) / kPostRows; }
+
+hipError_t post(hipStream_t s, const SmallArgs &a, const double *v, double *qs, double *q2,
+                double *stats, int *nblocks_out) {
+  const int nb = post_blocks(a.L);
   if (nblocks_out) *nblocks_out = nb;
-  hipLaunchKernelGGL((k_post<T>), dim3(nb, (a.kp + 63) / 64), dim3(64, 4), 0, s, a, P2, zstride, nchunk,
-                     qs, q2, vT, stats);
+  hipLaunchKernelGGL(k_post, dim3(nb, (a.kp + 63) / 64), dim3(64, 4), 0, s, a, v, qs, q2, stats);
   return hipGetLastError();
 }
-template hipError_t post<float>(hipStream_t, const SmallArgs &, const double *, size_t, int, double *, double *, float *, double *, int *);
-template hipError_t post<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, double *, double *, double *, double *, int *);
 
 template <typename T>
 __global__ void k_shot_scaled(SmallArgs a, const double *__restrict__ q2, T *__restrict__ that) {

@@ -97,6 +97,7 @@ _SIGS = {
     "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_batch_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ladmm_batch_tiles": (C.c_int, [C.c_void_p, _IP, _IP]),
     "ladmm_batch_kernel_times": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_Weights),
                                     C.POINTER(C.c_uint64), C.POINTER(_Opts), C.POINTER(_Result)]),
@@ -315,6 +316,11 @@ class Batch:
 
     KERNEL_CLASSES = ("gemm1", "rhs", "schur_solve", "post", "gemm2", "objective",
                       "shot_scale", "finalize")
+
+    def tiles(self):
+        a, b = C.c_int32(), C.c_int32()
+        _check(library().ladmm_batch_tiles(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def set_profiling(self, on=True):
         _check(library().ladmm_batch_set_profiling(self._h, 1 if on else 0))
