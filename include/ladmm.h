@@ -196,6 +196,10 @@ int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_i
  * in the order of any floating-point sum, so the choice never changes a result.
  * Values are indices into the library's configuration tables. */
 int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2);
+/* Pin the tile configurations (no autotuning), for reproducible benchmarks.
+ * An index that is not valid for the batch's shapes falls back to 0.
+ * LADMM_E_INVALID for an index outside [0, 4). */
+int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2);
 int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
 int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
 

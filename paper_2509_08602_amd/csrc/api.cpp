@@ -136,7 +136,8 @@ struct ladmm_batch {
   ladmm_case *c = nullptr;
   int k = 0, kp = 0, mask_words = 0;
   hipStream_t stream = nullptr;
-  void *q = nullptr;          // Np x kp (T)
+  void *q = nullptr;          // Np x kp (T): q = z1 + y1 of the dose points
+  void *W = nullptr;          // Np x kp (T): W = z1 - y1, input of the next GEMM1
   double *qs = nullptr;       // n_sec x kp
   double *q2 = nullptr;       // mAp x kp
   void *utab = nullptr;       // (G + 1) x kp (T)
@@ -295,7 +296,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   // GEMM split factors depend on the case only, so a plan's arithmetic does
   // not depend on how many other plans share its batch.
   c->nchunk1 = std::max(1, std::min((1024 + c->ntp / 64 - 1) / (c->ntp / 64), c->Np / 256));
-  c->nchunk2 = std::max(1, std::min(8, (256 + c->mAp / 64 - 1) / (c->mAp / 64)));
+  c->nchunk2 = std::max(1, std::min(16, (512 + c->mAp / 64 - 1) / (c->mAp / 64)));
 
   auto cleanup = [&](int rc) {
     for (void *p : c->allocs) hipFree(p);
@@ -522,11 +523,12 @@ int upload_tables(ladmm_batch *b, const uint64_t *ld_mask) {
       if (c->groups[g].type != LADMM_PT_LD) continue;
       for (int j = 0; j < k; ++j) cnt[(size_t)g * kp + j] = 0;
     }
+    const int cw = (c->N + 63) / 64;   // caller's words per plan row
     for (int pnt = 0; pnt < c->N; ++pnt) {
       const int g = c->hgrp[pnt];
       if (c->groups[g].type != LADMM_PT_LD) continue;
       for (int j = 0; j < k; ++j) {
-        const uint64_t wd = ld_mask[(size_t)j * b->mask_words + (pnt >> 6)];
+        const uint64_t wd = ld_mask[(size_t)j * cw + (pnt >> 6)];
         if ((wd >> (pnt & 63)) & 1ull) cnt[(size_t)g * kp + j]++;
       }
     }
@@ -569,8 +571,13 @@ int upload_tables(ladmm_batch *b, const uint64_t *ld_mask) {
   HIPC(hipMemcpy(b->wbot, wbot.data(), kp * sizeof(double), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(b->bbot, bbot.data(), bbot.size() * sizeof(double), hipMemcpyHostToDevice));
   if (ld_mask) {
+    // device rows are padded to the padded point count; padding bits are zero
+    const int cw = (c->N + 63) / 64;
     std::vector<uint64_t> m((size_t)kp * b->mask_words, 0);
-    std::memcpy(m.data(), ld_mask, (size_t)k * b->mask_words * sizeof(uint64_t));
+    for (int j = 0; j < k; ++j) {
+      std::memcpy(&m[(size_t)j * b->mask_words], ld_mask + (size_t)j * cw, cw * sizeof(uint64_t));
+      if (c->N % 64) m[(size_t)j * b->mask_words + cw - 1] &= (1ull << (c->N % 64)) - 1;
+    }
     HIPC(hipMemcpy(b->mask, m.data(), m.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
   }
   HIPC(hipMemcpy(b->active, b->h_active.data(), kp * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -642,6 +649,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   const int kp = b->kp;
   void *p;
   B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * Tsz)); b->q = p;
+  B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * Tsz)); b->W = p;
   B_RC(batch_alloc(b, &p, (size_t)c->n_sec * kp * sizeof(double))); b->qs = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->q2 = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)(c->G + 1) * kp * Tsz)); b->utab = p;
@@ -670,6 +678,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)kp * kFinal * sizeof(double))); b->fin = (double *)p;
   B_HIP(hipHostMalloc((void **)&b->h_fin, (size_t)kp * kFinal * sizeof(double), hipHostMallocDefault));
   B_HIP(hipMemsetAsync(b->q, 0, (size_t)c->Np * kp * Tsz, b->stream));
+  B_HIP(hipMemsetAsync(b->W, 0, (size_t)c->Np * kp * Tsz, b->stream));
   B_HIP(hipMemsetAsync(b->qs, 0, (size_t)c->n_sec * kp * sizeof(double), b->stream));
   B_HIP(hipMemsetAsync(b->q2, 0, (size_t)c->mAp * kp * sizeof(double), b->stream));
   B_HIP(hipStreamSynchronize(b->stream));
@@ -723,8 +732,8 @@ int iterate_once(ladmm_batch *b, bool stats) {
   const int kp = b->kp;
   PointTable<T> pt = point_table<T>(b);
   SmallArgs sa = small_args(b);
-  PROF(0, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->q, kp, (T *)b->P1, kp, c->ntp,
-                      kp, c->Np, c->nchunk1, &pt, b->cfg1)));
+  PROF(0, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1, kp, c->ntp,
+                      kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
   PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
   PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
                            c->nchunk2, nullptr)));
@@ -732,6 +741,7 @@ int iterate_once(ladmm_batch *b, bool stats) {
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
   EpiArgs<T> ea{};
   ea.q = (T *)b->q;
+  ea.w = (T *)b->W;
   ea.ldq = kp;
   ea.invrho = b->invrho;
   ea.active = b->active;
@@ -800,6 +810,7 @@ int autotune(ladmm_batch *b) {
   hipError_t e = hipMemsetAsync(noact, 0, kp * sizeof(int32_t), s);
   EpiArgs<T> ea{};
   ea.q = (T *)b->q;
+  ea.w = (T *)b->W;
   ea.ldq = kp;
   ea.invrho = b->invrho;
   ea.active = noact;
@@ -813,8 +824,8 @@ int autotune(ladmm_batch *b) {
       for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
         e = hipEventRecord(b->ev0, s);
         if (e == hipSuccess)
-          e = which == 0 ? gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->q, kp, (T *)b->P1,
-                                      kp, c->ntp, kp, c->Np, c->nchunk1, &pt, cfg)
+          e = which == 0 ? gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1,
+                                      kp, c->ntp, kp, c->Np, c->nchunk1, nullptr, cfg)
                          : gemm_nn<T>(s, EPI_ADMM, (const T *)c->D, c->ntp, (const T *)b->vT, kp,
                                       c->Np, kp, c->ntp, ea, cfg);
         if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
@@ -1123,10 +1134,17 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const
   if (e == hipSuccess) e = hipMemcpy(dz, z1, (size_t)N * k * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dy, y1, (size_t)N * k * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
-    if (c->precision == LADMM_F64)
+    if (c->precision == LADMM_F64) {
       e = import_points<double>(b->stream, (double *)b->q, kp, N, k, dz, dy);
-    else
+      if (e == hipSuccess)
+        e = w_from_q<double>(b->stream, (const double *)b->q, (double *)b->W, c->Np, kp,
+                             point_table<double>(b));
+    } else {
       e = import_points<float>(b->stream, (float *)b->q, kp, N, k, dz, dy);
+      if (e == hipSuccess)
+        e = w_from_q<float>(b->stream, (const float *)b->q, (float *)b->W, c->Np, kp,
+                            point_table<float>(b));
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   hipFree(dz);
@@ -1168,6 +1186,17 @@ int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
   if (gemm1) *gemm1 = b->cfg1;
   if (gemm2) *gemm2 = b->cfg2;
+  return LADMM_OK;
+}
+
+int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (gemm1 < 0 || gemm1 >= kGemmCfgs || gemm2 < 0 || gemm2 >= kGemmCfgs)
+    return fail(LADMM_E_INVALID, "tile configuration out of range");
+  b->cfg1 = gemm_tn_cfg_ok(gemm1, b->c->ntp, b->kp) ? gemm1 : 0;
+  b->cfg2 = gemm_nn_cfg_ok(gemm2, b->c->Np, b->kp) ? gemm2 : 0;
+  b->tuned = true;
+  set_row_blocks(b);
   return LADMM_OK;
 }
 

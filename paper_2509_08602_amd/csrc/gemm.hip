@@ -403,9 +403,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
           T *qp = ea.q + (size_t)m * ea.ldq + n;
           const T qv = *qp;
           const T z = clip0u(qv, u);
-          // q' = x1 + y1 = z1 - c/rho - A_s' v, with c_p = -sign_p
+          // q' = x1 + y1 = z1 - c/rho - A_s' v, with c_p = -sign_p; the next
+          // right-hand-side product needs W' = z1' - y1' = 2 clip(q') - q'
           const T qn = z + sg * (T)ea.invrho[n] - s;
-          if (ea.active[n]) *qp = qn;
+          if (ea.active[n]) {
+            *qp = qn;
+            ea.w[(size_t)m * ea.ldq + n] = T(2) * clip0u(qn, u) - qn;
+          }
           if (EPI == EPI_ADMM_STATS) {
             const double yo = (double)qv - (double)z;
             const double zn = (double)clip0u(qn, u);
@@ -513,5 +517,29 @@ template hipError_t gemm_nn<float>(hipStream_t, int, const float *, int, const f
                                    int, int, const EpiArgs<float> &, int);
 template hipError_t gemm_nn<double>(hipStream_t, int, const double *, int, const double *, int,
                                     int, int, int, const EpiArgs<double> &, int);
+
+}  // namespace ladmm
+
+namespace ladmm {
+
+template <typename T>
+__global__ void k_w_from_q(const T *__restrict__ q, T *__restrict__ w, int Np, int kp,
+                           PointTable<T> pt) {
+  const size_t total = (size_t)Np * kp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / kp), j = (int)(e % kp);
+    const T qv = q[e];
+    w[e] = T(2) * clip0u(qv, upper_of(pt, pt.grp[p], p, j)) - qv;
+  }
+}
+
+template <typename T>
+hipError_t w_from_q(hipStream_t s, const T *q, T *w, int Np, int kp, const PointTable<T> &pt) {
+  hipLaunchKernelGGL((k_w_from_q<T>), dim3(2048), dim3(256), 0, s, q, w, Np, kp, pt);
+  return hipGetLastError();
+}
+template hipError_t w_from_q<float>(hipStream_t, const float *, float *, int, int, const PointTable<float> &);
+template hipError_t w_from_q<double>(hipStream_t, const double *, double *, int, int, const PointTable<double> &);
 
 }  // namespace ladmm

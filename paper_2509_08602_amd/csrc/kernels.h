@@ -54,6 +54,7 @@ template <typename T>
 struct EpiArgs {
   T *C; int ldc;                   // EPI_STORE output
   T *q; int ldq;                   // EPI_ADMM: iterate q (in place)
+  T *w;                            // EPI_ADMM: W = z1 - y1 of the new iterate (ld = ldq)
   const double *invrho;            // per plan 1/rho
   const int32_t *active;           // per plan
   double *stats; int nstat_cols;   // partial stats [blockIdx.x][stat][nstat_cols]
@@ -143,6 +144,10 @@ hipError_t alg1_select(hipStream_t s, int k, int64_t n_vox, const uint64_t *vols
 // bits[j][v / 64] bit v % 64 = (lo <= d[v][j] < hi), d: n_vox rows of ldd.
 hipError_t band_bits(hipStream_t s, const double *d, int ldd, int n_vox, int k, double lo, double hi,
                      uint64_t *bits);
+
+// W = 2 clip(q, 0, u) - q for every point and plan (Np x kp), after a state import.
+template <typename T>
+hipError_t w_from_q(hipStream_t s, const T *q, T *w, int Np, int kp, const PointTable<T> &pt);
 
 // ---- state conversion ---------------------------------------------------------
 template <typename T>

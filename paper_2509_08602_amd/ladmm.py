@@ -98,6 +98,7 @@ _SIGS = {
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_batch_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_tiles": (C.c_int, [C.c_void_p, _IP, _IP]),
+    "ladmm_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "ladmm_batch_kernel_times": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_solve_batch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(_Weights),
                                     C.POINTER(C.c_uint64), C.POINTER(_Opts), C.POINTER(_Result)]),
@@ -321,6 +322,9 @@ class Batch:
         a, b = C.c_int32(), C.c_int32()
         _check(library().ladmm_batch_tiles(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def set_tiles(self, gemm1, gemm2):
+        _check(library().ladmm_batch_set_tiles(self._h, int(gemm1), int(gemm2)))
 
     def set_profiling(self, on=True):
         _check(library().ladmm_batch_set_profiling(self._h, 1 if on else 0))

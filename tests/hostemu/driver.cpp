@@ -1,0 +1,132 @@
+// Drives libladmm's C ABI, built for the host emulation, on inputs written by
+// the Python test (tests/test_hostemu.py), and writes what it computed.
+//   driver <dir>   reads  <dir>/meta.txt, dose.f64, group.i32, groups.txt,
+//                          weights.f64 [, mask.u64] [, vols.u64, nld.i32] [, vox.f64]
+//                  writes <dir>/S.f64, Sinv.f64, E.f64, z1.f64, y1.f64, z2.f64,
+//                          y2.f64, res.f64 [, P.i64, masks.u64] [, band.u64]
+#include <cstdio>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "ladmm.h"
+
+template <typename T>
+static std::vector<T> load(const std::string &path, size_t n) {
+  std::vector<T> v(n);
+  FILE *f = fopen(path.c_str(), "rb");
+  if (!f) return {};
+  size_t got = fread(v.data(), sizeof(T), n, f);
+  fclose(f);
+  if (got != n) { fprintf(stderr, "short read %s\n", path.c_str()); exit(2); }
+  return v;
+}
+
+template <typename T>
+static void save(const std::string &path, const T *p, size_t n) {
+  FILE *f = fopen(path.c_str(), "wb");
+  fwrite(p, sizeof(T), n, f);
+  fclose(f);
+}
+
+#define CHECK(x)                                                           \
+  do {                                                                     \
+    int rc_ = (x);                                                         \
+    if (rc_ < 0) {                                                         \
+      fprintf(stderr, "%s failed: %d %s\n", #x, rc_, ladmm_last_error());  \
+      return 3;                                                            \
+    }                                                                      \
+  } while (0)
+
+int main(int argc, char **argv) {
+  if (argc < 2) return 1;
+  const std::string dir = argv[1];
+  std::ifstream meta(dir + "/meta.txt");
+  int N, n_iso, S, C, G, precision, k, iters, use_mask, n_vols, n_vox, band_vox, solve_iters;
+  int tile1 = -1, tile2 = -1;
+  double rho0, w0, D_T, phi_cal, d_ld, delta;
+  unsigned long long seed;
+  meta >> N >> n_iso >> S >> C >> G >> precision >> k >> iters >> rho0 >> w0 >> D_T >> phi_cal >>
+      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2;
+  const int n_t = n_iso * S * C, m_A = n_t + n_iso, n_A = N + n_iso * S;
+  auto dose = load<double>(dir + "/dose.f64", (size_t)N * n_t);
+  auto grp = load<int32_t>(dir + "/group.i32", N);
+  std::vector<ladmm_group> groups(G);
+  std::ifstream gf(dir + "/groups.txt");
+  for (auto &g : groups) gf >> g.type >> g.structure >> g.threshold >> g.share;
+  auto wv = load<double>(dir + "/weights.f64", (size_t)k * 4);
+  std::vector<ladmm_weights> w(k);
+  for (int j = 0; j < k; ++j) w[j] = {wv[4 * j], wv[4 * j + 1], wv[4 * j + 2], wv[4 * j + 3]};
+
+  ladmm_ctx *ctx = nullptr;
+  CHECK(ladmm_ctx_create(0, 0, &ctx));
+  ladmm_case_desc d{};
+  d.n_points = N; d.n_iso = n_iso; d.n_sectors = S; d.n_collimators = C;
+  d.dose = dose.data(); d.point_group = grp.data(); d.n_groups = G; d.groups = groups.data();
+  d.prescription_mean = D_T; d.phi_cal = phi_cal; d.precision = precision; d.row_normalize = 1;
+  d.beta = 0.0; d.beta_denominator = 2000.0;
+  ladmm_case *cs = nullptr;
+  CHECK(ladmm_create_case(ctx, &d, &cs));
+  std::vector<double> Sm((size_t)m_A * m_A), Si((size_t)m_A * m_A), E(m_A);
+  double beta = 0;
+  CHECK(ladmm_case_schur(cs, Sm.data(), Si.data()));
+  CHECK(ladmm_case_scaling(cs, E.data(), &beta));
+  save(dir + "/S.f64", Sm.data(), Sm.size());
+  save(dir + "/Sinv.f64", Si.data(), Si.size());
+  save(dir + "/E.f64", E.data(), E.size());
+
+  const int W = (N + 63) / 64;
+  std::vector<uint64_t> mask;
+  if (use_mask) mask = load<uint64_t>(dir + "/mask.u64", (size_t)k * W);
+  ladmm_opts o{};
+  o.max_iter = 1000; o.check_every = 7; o.tol_gap = 0.0; o.tol_pri = 1; o.tol_dual = 1;
+  o.rho0 = rho0; o.w0_bot = w0;
+  ladmm_batch *b = nullptr;
+  CHECK(ladmm_batch_create(cs, k, w.data(), use_mask ? mask.data() : nullptr, nullptr, &o, &b));
+  if (tile1 >= 0) CHECK(ladmm_batch_set_tiles(b, tile1, tile2));
+  CHECK(ladmm_batch_iterate(b, iters));
+  std::vector<double> z1((size_t)n_A * k), y1((size_t)n_A * k), z2((size_t)m_A * k), y2((size_t)m_A * k);
+  CHECK(ladmm_batch_export(b, z1.data(), y1.data(), z2.data(), y2.data()));
+  save(dir + "/z1.f64", z1.data(), z1.size());
+  save(dir + "/y1.f64", y1.data(), y1.size());
+  save(dir + "/z2.f64", z2.data(), z2.size());
+  save(dir + "/y2.f64", y2.data(), y2.size());
+  std::vector<double> res((size_t)k * 5), t((size_t)k * n_t), bot((size_t)k * n_iso);
+  std::vector<int32_t> it(k), st(k);
+  ladmm_result r{t.data(), bot.data(), &res[0], &res[k], &res[2 * k], &res[3 * k], &res[4 * k],
+                 it.data(), st.data()};
+  CHECK(ladmm_batch_results(b, &r));
+  save(dir + "/res.f64", res.data(), res.size());
+  save(dir + "/t.f64", t.data(), t.size());
+  if (band_vox > 0) {
+    auto vox = load<double>(dir + "/vox.f64", (size_t)band_vox * n_t);
+    std::vector<uint64_t> bits((size_t)k * ((band_vox + 63) / 64));
+    CHECK(ladmm_batch_ld_band(b, band_vox, vox.data(), d_ld, delta, bits.data()));
+    save(dir + "/band.u64", bits.data(), bits.size());
+  }
+  // re-import the exported state and continue (exercises import and W rebuild)
+  CHECK(ladmm_batch_import(b, z1.data(), y1.data(), z2.data(), y2.data()));
+  CHECK(ladmm_batch_iterate(b, 1));
+  CHECK(ladmm_batch_export(b, z1.data(), y1.data(), z2.data(), y2.data()));
+  save(dir + "/z1b.f64", z1.data(), z1.size());
+  CHECK(ladmm_batch_destroy(b));
+  if (solve_iters > 0) {
+    ladmm_opts so = o;
+    so.max_iter = solve_iters; so.check_every = 5; so.tol_gap = 1e-6; so.tol_pri = 1e-6; so.tol_dual = 1e-6;
+    CHECK(ladmm_solve_batch(cs, k, w.data(), use_mask ? mask.data() : nullptr, &so, &r));
+  }
+  if (n_vols > 0) {
+    const int Wv = (n_vox + 63) / 64;
+    auto vols = load<uint64_t>(dir + "/vols.u64", (size_t)n_vols * Wv);
+    auto nld = load<int32_t>(dir + "/nld.i32", n_vols);
+    std::vector<int64_t> P(n_vox);
+    std::vector<uint64_t> masks((size_t)n_vols * Wv);
+    int64_t nP = 0;
+    CHECK(ladmm_select_ld_points(ctx, n_vols, n_vox, vols.data(), nld.data(), seed, P.data(), &nP, masks.data()));
+    save(dir + "/P.i64", P.data(), (size_t)nP);
+    save(dir + "/masks.u64", masks.data(), masks.size());
+  }
+  CHECK(ladmm_destroy_case(cs));
+  CHECK(ladmm_ctx_destroy(ctx));
+  return 0;
+}
