@@ -105,6 +105,8 @@ typedef struct {
   int32_t check_every;
   double tol_gap, tol_pri, tol_dual;
   double rho0, w0_bot;
+  int32_t autotune;   /* nonzero: time the tile configurations before the first
+                         iteration (see ladmm_batch_tiles); 0: configuration 0 */
 } ladmm_opts;
 
 /* Per-plan results; every pointer is caller-owned host memory or NULL.
@@ -234,6 +236,40 @@ int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, do
 int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint64_t *vol_bits,
                            const int32_t *n_ld, uint64_t seed, int64_t *P, int64_t *nP,
                            uint64_t *masks);
+
+/* Second pass of the two-pass optimisation (Sec. 2.C): how the low-dose points
+ * of the second-pass problem are chosen from the first-pass dose.
+ *   n_vox, phi_vox: candidate voxels of the patient volume and their dose rates
+ *                   (host, n_vox x n_t, >= 0); the low-dose volume V_j of plan j
+ *                   is {v : d_ld <= d_j(v) < d_ld + delta} for the pass-1 dose d_j.
+ *   n_ld:           host, k desired point counts N_LD,j (> 0 to sample plan j).
+ *   seed:           seed of Algorithm 1's selections.
+ *   ld_group:       index (in the pass-1 descriptor's groups) of the low-dose group
+ *                   whose points are replaced; every other point is kept as is. */
+typedef struct {
+  int64_t n_vox;
+  const double *phi_vox;
+  double d_ld, delta;
+  const int32_t *n_ld;
+  uint64_t seed;
+  int32_t ld_group;
+} ladmm_pass2_desc;
+
+/* Both passes for k plans: pass 1 on `pass1`, the band and Algorithm 1 on the
+ * device, a new case whose low-dose block is the shared point set P (new row
+ * scales, beta, Schur complement and factor, Sec. 2.C.2), and pass 2 with plan
+ * j's low-dose bound u restricted to its own subset p_j.  Pass 2 starts from
+ * zero iterates.
+ *   pass1_out: optional per-plan results of pass 1 (NULL to skip).
+ *   out:       per-plan results of pass 2 (t in pass-2 shot order = pass-1 order).
+ *   P:         optional host output, capacity n_vox: the selected voxel indices.
+ *   n_points2: optional host output: |P| (first), then the pass-2 point count.
+ *   times_ms:  optional host output[5]: wall time of pass-1 setup, pass-1 solve,
+ *              band + Algorithm 1, pass-2 setup, pass-2 solve. */
+int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
+                   const ladmm_weights *w, const ladmm_opts *opts, const ladmm_pass2_desc *p2,
+                   ladmm_result *pass1_out, ladmm_result *out, int64_t *P, int64_t *n_points2,
+                   double *times_ms);
 
 /* Message for the last error returned on this thread ("" if none). */
 const char *ladmm_last_error(void);

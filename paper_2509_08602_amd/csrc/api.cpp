@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -851,8 +852,13 @@ int autotune(ladmm_batch *b) {
 int run_chunk(ladmm_batch *b, int n, bool decide) {
   if (n <= 0) return LADMM_OK;
   if (!b->tuned) {
-    int rc = b->c->precision == LADMM_F64 ? autotune<double>(b) : autotune<float>(b);
-    if (rc) return rc;
+    if (b->opts.autotune) {
+      int rc = b->c->precision == LADMM_F64 ? autotune<double>(b) : autotune<float>(b);
+      if (rc) return rc;
+    } else {
+      b->tuned = true;
+      set_row_blocks(b);
+    }
   }
   int n_active = 0;
   for (int j = 0; j < b->k; ++j) n_active += b->h_active[j] != 0;
@@ -1304,6 +1310,94 @@ int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint6
   if (s) hipStreamDestroy(s);
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("select_ld_points: ") + hipGetErrorString(e));
   *nP = hn;
+  return LADMM_OK;
+}
+
+int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const ladmm_weights *w,
+                   const ladmm_opts *opts, const ladmm_pass2_desc *p2, ladmm_result *pass1_out,
+                   ladmm_result *out, int64_t *P_out, int64_t *n_points2, double *times_ms) {
+  if (!ctx || !d1 || !w || !opts || !p2 || !out) return fail(LADMM_E_INVALID, "two_pass: null argument");
+  if (k < 1 || p2->n_vox < 1 || !p2->phi_vox || !p2->n_ld)
+    return fail(LADMM_E_INVALID, "two_pass: bad second-pass description");
+  if (p2->ld_group < 0 || p2->ld_group >= d1->n_groups || d1->groups[p2->ld_group].type != LADMM_PT_LD)
+    return fail(LADMM_E_INVALID, "two_pass: ld_group must name a low-dose group");
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  double tm[5] = {0, 0, 0, 0, 0};
+  const int n_t = d1->n_iso * d1->n_sectors * d1->n_collimators;
+  // pass 1
+  auto t0 = clk::now();
+  ladmm_case *c1 = nullptr;
+  int rc = ladmm_create_case(ctx, d1, &c1);
+  if (rc) return rc;
+  auto t1 = clk::now();
+  ladmm_batch *b1 = nullptr;
+  rc = ladmm_batch_create(c1, k, w, nullptr, nullptr, opts, &b1);
+  if (rc == LADMM_OK) rc = ladmm_batch_run(b1);
+  if (rc == LADMM_OK && pass1_out) rc = ladmm_batch_results(b1, pass1_out);
+  auto t2 = clk::now();
+  // low-dose band of the pass-1 dose, then Algorithm 1
+  const int64_t nv = p2->n_vox;
+  const int Wv = (int)((nv + 63) / 64);
+  std::vector<uint64_t> vol((size_t)k * Wv), masks((size_t)k * Wv);
+  std::vector<int64_t> P(nv);
+  int64_t nP = 0;
+  if (rc == LADMM_OK) rc = ladmm_batch_ld_band(b1, nv, p2->phi_vox, p2->d_ld, p2->delta, vol.data());
+  if (b1) ladmm_batch_destroy(b1);
+  ladmm_destroy_case(c1);
+  if (rc == LADMM_OK)
+    rc = ladmm_select_ld_points(ctx, k, nv, vol.data(), p2->n_ld, p2->seed, P.data(), &nP, masks.data());
+  if (rc) return rc;
+  auto t3 = clk::now();
+  // pass-2 case: every non-LD point of pass 1, then the points of P in the LD group
+  std::vector<int32_t> keep;
+  for (int p = 0; p < d1->n_points; ++p)
+    if (d1->point_group[p] != p2->ld_group) keep.push_back(p);
+  const int64_t N2 = (int64_t)keep.size() + nP;
+  if (N2 < 1 || N2 > INT32_MAX) return fail(LADMM_E_INVALID, "two_pass: empty or too large pass 2");
+  std::vector<double> dose2((size_t)N2 * n_t);
+  std::vector<int32_t> grp2(N2);
+  for (size_t i = 0; i < keep.size(); ++i) {
+    std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
+    grp2[i] = d1->point_group[keep[i]];
+  }
+  for (int64_t i = 0; i < nP; ++i) {
+    std::memcpy(&dose2[(keep.size() + i) * n_t], p2->phi_vox + (size_t)P[i] * n_t, n_t * sizeof(double));
+    grp2[keep.size() + i] = p2->ld_group;
+  }
+  const int W2 = (int)((N2 + 63) / 64);
+  std::vector<uint64_t> mask2((size_t)k * W2, 0);
+  for (int j = 0; j < k; ++j)
+    for (int64_t i = 0; i < nP; ++i)
+      if ((masks[(size_t)j * Wv + (i >> 6)] >> (i & 63)) & 1ull) {
+        const int64_t pt = (int64_t)keep.size() + i;
+        mask2[(size_t)j * W2 + (pt >> 6)] |= 1ull << (pt & 63);
+      }
+  ladmm_case_desc d2 = *d1;
+  d2.n_points = (int32_t)N2;
+  d2.dose = dose2.data();
+  d2.point_group = grp2.data();
+  ladmm_case *c2 = nullptr;
+  rc = ladmm_create_case(ctx, &d2, &c2);
+  if (rc) return rc;
+  auto t4 = clk::now();
+  ladmm_batch *b2 = nullptr;
+  rc = ladmm_batch_create(c2, k, w, mask2.data(), nullptr, opts, &b2);
+  if (rc == LADMM_OK) rc = ladmm_batch_run(b2);
+  if (rc == LADMM_OK) rc = ladmm_batch_results(b2, out);
+  auto t5 = clk::now();
+  if (b2) ladmm_batch_destroy(b2);
+  ladmm_destroy_case(c2);
+  if (rc) return rc;
+  tm[0] = ms(t0, t1); tm[1] = ms(t1, t2); tm[2] = ms(t2, t3); tm[3] = ms(t3, t4); tm[4] = ms(t4, t5);
+  if (times_ms) std::memcpy(times_ms, tm, sizeof(tm));
+  if (P_out) std::memcpy(P_out, P.data(), (size_t)nP * sizeof(int64_t));
+  if (n_points2) {
+    n_points2[0] = nP;
+    n_points2[1] = N2;
+  }
   return LADMM_OK;
 }
 

@@ -20,6 +20,7 @@
 // LDS padding: a half-wavefront (32 lanes) reads 16 consecutive words from
 // two rows; a row stride congruent to 16 (mod 32) words keeps the 32 banks
 // distinct (rows of k-contiguous tiles use a stride congruent to 2 instead).
+#pragma once
 #include "kernels.h"
 
 #include <math.h>
@@ -207,12 +208,6 @@ static int pick_bn(int N) {
 struct TnCfg { int bm, wm, wn; };
 static const TnCfg kTnCfgs[kGemmCfgs] = {{64, 2, 2}, {32, 2, 2}, {64, 4, 2}, {64, 4, 1}};
 
-bool gemm_tn_cfg_ok(int cfg, int M, int N) {
-  if (cfg < 0 || cfg >= kGemmCfgs) return false;
-  const TnCfg c = kTnCfgs[cfg];
-  const int BN = pick_bn(N);
-  return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
-}
 
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
@@ -456,17 +451,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
 struct NnCfg { int bm, wm, wn; };
 static const NnCfg kNnCfgs[kGemmCfgs] = {{128, 4, 1}, {64, 2, 2}, {128, 4, 2}, {64, 4, 2}};
 
-int gemm_nn_block_rows(int cfg, int M, int N) {
-  if (!gemm_nn_cfg_ok(cfg, M, N)) cfg = 0;
-  return kNnCfgs[cfg].bm;
-}
 
-bool gemm_nn_cfg_ok(int cfg, int M, int N) {
-  if (cfg < 0 || cfg >= kGemmCfgs) return false;
-  const NnCfg c = kNnCfgs[cfg];
-  const int BN = pick_bn(N);
-  return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
-}
 
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb, int M,
@@ -509,15 +494,6 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
   return hipGetLastError();
 }
 
-template hipError_t gemm_tn<float>(hipStream_t, const float *, int, const float *, int, float *,
-                                   int, int, int, int, int, const PointTable<float> *, int);
-template hipError_t gemm_tn<double>(hipStream_t, const double *, int, const double *, int,
-                                    double *, int, int, int, int, int, const PointTable<double> *, int);
-template hipError_t gemm_nn<float>(hipStream_t, int, const float *, int, const float *, int, int,
-                                   int, int, const EpiArgs<float> &, int);
-template hipError_t gemm_nn<double>(hipStream_t, int, const double *, int, const double *, int,
-                                    int, int, int, const EpiArgs<double> &, int);
-
 }  // namespace ladmm
 
 namespace ladmm {
@@ -539,7 +515,5 @@ hipError_t w_from_q(hipStream_t s, const T *q, T *w, int Np, int kp, const Point
   hipLaunchKernelGGL((k_w_from_q<T>), dim3(2048), dim3(256), 0, s, q, w, Np, kp, pt);
   return hipGetLastError();
 }
-template hipError_t w_from_q<float>(hipStream_t, const float *, float *, int, int, const PointTable<float> &);
-template hipError_t w_from_q<double>(hipStream_t, const double *, double *, int, int, const PointTable<double> &);
 
 }  // namespace ladmm

@@ -52,11 +52,17 @@ class _Weights(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("tol_gap", C.c_double),
                 ("tol_pri", C.c_double), ("tol_dual", C.c_double), ("rho0", C.c_double),
-                ("w0_bot", C.c_double)]
+                ("w0_bot", C.c_double), ("autotune", C.c_int32)]
 
 
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int32)
+
+
+class _Pass2(C.Structure):
+    _fields_ = [("n_vox", C.c_int64), ("phi_vox", C.POINTER(C.c_double)), ("d_ld", C.c_double),
+                ("delta", C.c_double), ("n_ld", C.POINTER(C.c_int32)), ("seed", C.c_uint64),
+                ("ld_group", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -107,6 +113,10 @@ _SIGS = {
     "ladmm_select_ld_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_uint64),
                                          _IP, C.c_uint64, C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ladmm_two_pass": (C.c_int, [C.c_void_p, C.POINTER(_CaseDesc), C.c_int32, C.POINTER(_Weights),
+                                 C.POINTER(_Opts), C.POINTER(_Pass2), C.c_void_p,
+                                 C.POINTER(_Result), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 _DP]),
     "ladmm_last_error": (C.c_char_p, []),
     "ladmm_version": (C.c_char_p, []),
 }
@@ -148,11 +158,12 @@ class Options:
     tol_dual: float = 1e-4
     rho0: float = 1000.0
     w0_bot: float = 1e-3
+    autotune: bool = True
 
     def c(self):
         return _Opts(int(self.max_iter), int(self.check_every), float(self.tol_gap),
                      float(self.tol_pri), float(self.tol_dual), float(self.rho0),
-                     float(self.w0_bot))
+                     float(self.w0_bot), 1 if self.autotune else 0)
 
 
 class Context:
@@ -178,6 +189,21 @@ class Context:
             pass
 
 
+def _case_desc(dose, point_group, groups, n_iso, n_sectors, n_collimators, prescription_mean,
+               phi_cal, precision, row_normalize=True, beta=None, beta_denominator=2000.0):
+    """The C descriptor plus the arrays it points to (kept alive by the caller)."""
+    dose = np.ascontiguousarray(dose, dtype=np.float64)
+    pg = np.ascontiguousarray(point_group, dtype=np.int32)
+    garr = (_Group * len(groups))(*[_Group(int(t), int(s), float(th), float(sh))
+                                    for (t, s, th, sh) in groups])
+    desc = _CaseDesc(dose.shape[0], int(n_iso), int(n_sectors), int(n_collimators),
+                     dose.ctypes.data_as(_DP), pg.ctypes.data_as(_IP), len(groups), garr,
+                     float(prescription_mean), float(phi_cal), PRECISIONS[precision],
+                     1 if row_normalize else 0, float(beta) if beta else 0.0,
+                     float(beta_denominator))
+    return desc, (dose, pg, garr)
+
+
 class Case:
     """A resident case: dose matrix, Schur complement factor and inverse in HBM."""
 
@@ -185,18 +211,12 @@ class Case:
                  n_collimators=3, prescription_mean=20.0, phi_cal=3.0, precision="f64",
                  row_normalize=True, beta=None, beta_denominator=2000.0):
         self.ctx = ctx
-        dose = np.ascontiguousarray(dose, dtype=np.float64)
-        pg = np.ascontiguousarray(point_group, dtype=np.int32)
-        garr = (_Group * len(groups))(*[_Group(int(t), int(s), float(th), float(sh))
-                                        for (t, s, th, sh) in groups])
-        self.n_points, self.n_t = dose.shape
+        desc, keep = _case_desc(dose, point_group, groups, n_iso, n_sectors, n_collimators,
+                                prescription_mean, phi_cal, precision, row_normalize, beta,
+                                beta_denominator)
+        self.n_points, self.n_t = keep[0].shape
         self.n_iso, self.n_sectors, self.n_collimators = int(n_iso), int(n_sectors), int(n_collimators)
         self.precision = precision
-        desc = _CaseDesc(self.n_points, self.n_iso, self.n_sectors, self.n_collimators,
-                         dose.ctypes.data_as(_DP), pg.ctypes.data_as(_IP), len(groups), garr,
-                         float(prescription_mean), float(phi_cal), PRECISIONS[precision],
-                         1 if row_normalize else 0, float(beta) if beta else 0.0,
-                         float(beta_denominator))
         self._h = C.c_void_p()
         _check(library().ladmm_create_case(ctx._h, C.byref(desc), C.byref(self._h)))
 
@@ -359,6 +379,43 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _result_buffers(k, n_t, n_iso):
+    out = dict(t=np.empty((k, n_t)), bot=np.empty((k, n_iso)), objective=np.empty(k),
+               dual_obj=np.empty(k), rel_gap=np.empty(k), r_pri=np.empty(k), r_dual=np.empty(k),
+               iters=np.empty(k, np.int32), plan_status=np.empty(k, np.int32))
+    r = _Result(_dptr(out["t"]), _dptr(out["bot"]), _dptr(out["objective"]), _dptr(out["dual_obj"]),
+                _dptr(out["rel_gap"]), _dptr(out["r_pri"]), _dptr(out["r_dual"]),
+                out["iters"].ctypes.data_as(_IP), out["plan_status"].ctypes.data_as(_IP))
+    return out, r
+
+
+def two_pass(ctx: Context, case, weights, phi_vox, d_ld, delta, n_ld, seed, ld_group,
+             precision="f64", opts: Options | None = None):
+    """ladmm_two_pass: both passes for every plan (case: a synthetic-case-like object).
+
+    Returns (pass1 results, pass2 results, P, n_points2, times_ms)."""
+    groups = [(g.type, g.structure, g.threshold, g.share) for g in case.groups]
+    desc, keep = _case_desc(case.dose, case.group, groups, case.n_iso, case.n_sectors,
+                            case.n_collimators, case.prescription_mean, case.phi_cal, precision)
+    w, k = _weights(weights)
+    phi = np.ascontiguousarray(phi_vox, np.float64)
+    nld = np.ascontiguousarray(np.broadcast_to(np.asarray(n_ld, np.int32), (k,)))
+    p2 = _Pass2(phi.shape[0], _dptr(phi), float(d_ld), float(delta), nld.ctypes.data_as(_IP),
+                C.c_uint64(int(seed) & ((1 << 64) - 1)), int(ld_group))
+    n_t = case.dose.shape[1]
+    out1, r1 = _result_buffers(k, n_t, case.n_iso)
+    out2, r2 = _result_buffers(k, n_t, case.n_iso)
+    P = np.zeros(phi.shape[0], np.int64)
+    n2 = np.zeros(2, np.int64)
+    times = np.zeros(5)
+    o = (opts or Options()).c()
+    _check(library().ladmm_two_pass(ctx._h, C.byref(desc), k, w, C.byref(o), C.byref(p2),
+                                    C.cast(C.pointer(r1), C.c_void_p), C.byref(r2),
+                                    P.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    n2.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(times)))
+    return out1, out2, P[:n2[0]], int(n2[1]), times
 
 
 def solve_batch(case: Case, weights, ld_mask=None, opts: Options | None = None):

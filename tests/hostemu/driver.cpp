@@ -43,11 +43,11 @@ int main(int argc, char **argv) {
   const std::string dir = argv[1];
   std::ifstream meta(dir + "/meta.txt");
   int N, n_iso, S, C, G, precision, k, iters, use_mask, n_vols, n_vox, band_vox, solve_iters;
-  int tile1 = -1, tile2 = -1;
+  int tile1 = -1, tile2 = -1, run_two_pass = 0;
   double rho0, w0, D_T, phi_cal, d_ld, delta;
   unsigned long long seed;
   meta >> N >> n_iso >> S >> C >> G >> precision >> k >> iters >> rho0 >> w0 >> D_T >> phi_cal >>
-      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2;
+      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2 >> run_two_pass;
   const int n_t = n_iso * S * C, m_A = n_t + n_iso, n_A = N + n_iso * S;
   auto dose = load<double>(dir + "/dose.f64", (size_t)N * n_t);
   auto grp = load<int32_t>(dir + "/group.i32", N);
@@ -80,7 +80,7 @@ int main(int argc, char **argv) {
   if (use_mask) mask = load<uint64_t>(dir + "/mask.u64", (size_t)k * W);
   ladmm_opts o{};
   o.max_iter = 1000; o.check_every = 7; o.tol_gap = 0.0; o.tol_pri = 1; o.tol_dual = 1;
-  o.rho0 = rho0; o.w0_bot = w0;
+  o.rho0 = rho0; o.w0_bot = w0; o.autotune = 1;
   ladmm_batch *b = nullptr;
   CHECK(ladmm_batch_create(cs, k, w.data(), use_mask ? mask.data() : nullptr, nullptr, &o, &b));
   if (tile1 >= 0) CHECK(ladmm_batch_set_tiles(b, tile1, tile2));
@@ -98,7 +98,7 @@ int main(int argc, char **argv) {
   CHECK(ladmm_batch_results(b, &r));
   save(dir + "/res.f64", res.data(), res.size());
   save(dir + "/t.f64", t.data(), t.size());
-  if (band_vox > 0) {
+  if (band_vox > 0 && !run_two_pass) {
     auto vox = load<double>(dir + "/vox.f64", (size_t)band_vox * n_t);
     std::vector<uint64_t> bits((size_t)k * ((band_vox + 63) / 64));
     CHECK(ladmm_batch_ld_band(b, band_vox, vox.data(), d_ld, delta, bits.data()));
@@ -125,6 +125,29 @@ int main(int argc, char **argv) {
     CHECK(ladmm_select_ld_points(ctx, n_vols, n_vox, vols.data(), nld.data(), seed, P.data(), &nP, masks.data()));
     save(dir + "/P.i64", P.data(), (size_t)nP);
     save(dir + "/masks.u64", masks.data(), masks.size());
+  }
+  if (band_vox > 0 && run_two_pass) {
+    // both passes, a few fixed iterations each
+    auto vox = load<double>(dir + "/vox.f64", (size_t)band_vox * n_t);
+    int ld_group = -1;
+    for (int g = 0; g < G; ++g)
+      if (groups[g].type == LADMM_PT_LD) ld_group = g;
+    std::vector<int32_t> nld(k, 25);
+    ladmm_pass2_desc p2{band_vox, vox.data(), d_ld, delta, nld.data(), seed + 1, ld_group};
+    ladmm_opts to = o;
+    to.max_iter = 6; to.check_every = 3; to.tol_gap = 0.0; to.autotune = 0;
+    std::vector<double> t1((size_t)k * n_t), t2((size_t)k * n_t), f2(k);
+    std::vector<int32_t> it1(k), st1(k), it2(k), st2(k);
+    ladmm_result r1{t1.data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, it1.data(), st1.data()};
+    ladmm_result r2{t2.data(), nullptr, f2.data(), nullptr, nullptr, nullptr, nullptr, it2.data(), st2.data()};
+    std::vector<int64_t> P(band_vox);
+    int64_t n2[2] = {0, 0};
+    double times[5];
+    CHECK(ladmm_two_pass(ctx, &d, k, w.data(), &to, &p2, &r1, &r2, P.data(), n2, times));
+    save(dir + "/tp_t1.f64", t1.data(), t1.size());
+    save(dir + "/tp_t2.f64", t2.data(), t2.size());
+    save(dir + "/tp_f2.f64", f2.data(), f2.size());
+    save(dir + "/tp_P.i64", P.data(), (size_t)n2[0]);
   }
   CHECK(ladmm_destroy_case(cs));
   CHECK(ladmm_ctx_destroy(ctx));

@@ -42,7 +42,7 @@ def test_binding_struct_layouts_match_header():
     from paper_2509_08602_amd import ladmm
     assert ctypes.sizeof(ladmm._Group) == 24
     assert ctypes.sizeof(ladmm._Weights) == 32
-    assert ctypes.sizeof(ladmm._Opts) == 48
+    assert ctypes.sizeof(ladmm._Opts) == 56
     assert ctypes.sizeof(ladmm._Result) == 72
     assert ctypes.sizeof(ladmm._CaseDesc) == 88
 

@@ -66,7 +66,8 @@ def driver():
 
 
 def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, seed=0,
-                 vox=None, d_ld=0.0, delta=1.0, solve_iters=0, rho0=1000.0, tiles=(-1, -1)):
+                 vox=None, d_ld=0.0, delta=1.0, solve_iters=0, rho0=1000.0, tiles=(-1, -1),
+                 two_pass=False):
     os.makedirs(d, exist_ok=True)
     k = w.shape[0]
     n_vols = 0 if vols is None else vols.shape[0]
@@ -77,7 +78,7 @@ def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, 
                 f"{len(case.groups)} {0 if precision == 'f64' else 1} {k} {iters} {rho0!r} "
                 f"{cases.W0_BOT!r} {case.prescription_mean!r} {case.phi_cal!r} "
                 f"{0 if mask is None else 1} {n_vols} {n_vox} {seed} {band} {d_ld!r} {delta!r} "
-                f"{solve_iters} {tiles[0]} {tiles[1]}\n")
+                f"{solve_iters} {tiles[0]} {tiles[1]} {int(two_pass)}\n")
     np.ascontiguousarray(case.dose, np.float64).tofile(os.path.join(d, "dose.f64"))
     np.ascontiguousarray(case.group, np.int32).tofile(os.path.join(d, "group.i32"))
     with open(os.path.join(d, "groups.txt"), "w") as f:
@@ -178,3 +179,32 @@ def test_emulated_ld_mask_oar_band_and_alg1(driver, tmp_path):
     band = cases.unpack_bits(rd(d, "band.u64", (4, (333 + 63) // 64), np.uint64), 333)
     ref = odose.ld_band(odose.dose(vox, t.T), 0.05, 0.1)
     assert np.array_equal(band, ref)
+
+
+def test_emulated_two_pass(driver, tmp_path):
+    """Both passes through ladmm_two_pass: the pass-2 point set equals the oracle's
+    band + Algorithm 1 from the pass-1 shot times, and the pass-2 objective is the
+    oracle's F of the returned shot times on the rebuilt case."""
+    case = small_case(5)
+    w = cases.random_weights(2, 8)
+    cand = case.ld_candidates[::7][:200]
+    vox = case.kernel.dose_rate(cand)
+    d = str(tmp_path / "tp")
+    write_inputs(d, case, w, "f64", 2, seed=41, vox=vox, d_ld=0.05, delta=0.1, tiles=(1, 3),
+                 two_pass=True)
+    run(driver, d)
+    k, n_t = w.shape[0], case.n_t
+    t1 = rd(d, "tp_t1.f64", (k, n_t))
+    vols = odose.ld_band(odose.dose(vox, t1.T), 0.05, 0.1)
+    Pref, pref = oalg1.select_ld_points(vols, np.full(k, 25), 42)
+    P = np.fromfile(os.path.join(d, "tp_P.i64"), np.int64)
+    assert P.tolist() == Pref
+    ld_group = [g.type for g in case.groups].index(cases.LD)
+    keep = np.nonzero(case.group != ld_group)[0]
+    case2 = case.with_points(keep, extra_ld=cand[np.array(Pref, dtype=np.int64)], ld_group=ld_group)
+    mask2 = np.zeros((k, case2.n_points), bool)
+    if len(Pref):
+        mask2[:, len(keep):] = oalg1.masks_over(Pref, pref)
+    t2 = rd(d, "tp_t2.f64", (k, n_t))
+    F2 = olp.planning_objective(case2, w, t2.T, mask2)[0]
+    assert rel_err(rd(d, "tp_f2.f64", (k,)), F2) < 1e-10
