@@ -271,6 +271,81 @@ int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
                    ladmm_result *pass1_out, ladmm_result *out, int64_t *P, int64_t *n_points2,
                    double *times_ms);
 
+/* ---- Serving: continuous batching of plan requests ---------------------------
+ *
+ * Plans of one case are independent columns that share the dose block and the
+ * Schur complement inverse (end of Sec. 2.B); only b, u and the step size
+ * (Eq. rho_rule) are per plan.  A server keeps one slot batch ("lane") per case
+ * with work and one worker thread.  Between chunks of check_every iterations it
+ * retires finished plans and admits queued ones (oldest request first) into the
+ * free slots; lanes of different cases run on their own streams and overlap on
+ * the device.  A plan's arithmetic does not depend on the other slots, so its
+ * result is bitwise that of ladmm_solve_batch on the plan alone with the same
+ * options (max_iter a multiple of check_every).  Lane memory is charged to the
+ * context's HBM budget: when a new lane does not fit, idle lanes are released
+ * (least recently used first) and otherwise the request waits for busy lanes;
+ * a request that cannot fit even on an otherwise empty device fails with
+ * LADMM_E_NOMEM.
+ *
+ *   slots:       plan columns per lane, rounded up to a multiple of 32; [1, 4096].
+ *   check_every: iterations per chunk; admission, the stopping test and
+ *                retirement happen between chunks.  >= 1.
+ *   max_lanes:   at most this many cases hold lane memory at once (0: no limit
+ *                besides the HBM budget).
+ *   autotune:    time the tile configurations when a lane is created. */
+typedef struct {
+  int32_t slots;
+  int32_t check_every;
+  int32_t max_lanes;
+  int32_t autotune;
+} ladmm_server_opts;
+
+/* Counters of a server.  Latencies (submit to final status, completed requests
+ * only) are nearest-rank percentiles in milliseconds; busy_ms is the wall time
+ * of worker rounds that ran at least one lane; plan_iterations counts every
+ * iteration of every occupied slot. */
+typedef struct {
+  int64_t submitted, completed, cancelled, failed;
+  int64_t plans_completed, plan_iterations;
+  double p50_ms, p99_ms, max_ms, mean_ms, busy_ms;
+  int32_t lanes, busy_slots;
+} ladmm_server_stats;
+
+typedef struct ladmm_server ladmm_server;
+
+/* Start a server (and its worker thread) on a context.  The context must
+ * outlive the server.  LADMM_E_INVALID for options out of range. */
+int ladmm_server_create(ladmm_ctx *ctx, const ladmm_server_opts *opts, ladmm_server **out);
+/* Stop the worker, cancel every request that is not final, release the lanes
+ * and the server.  No other call on the server may be in progress or follow. */
+int ladmm_server_destroy(ladmm_server *s);
+/* Queue k plans of case c (same context as the server).  w, ld_mask (NULL or
+ * k rows of ceil(n_points/64) words, bit p of a row = LD point p kept, as in
+ * ladmm_batch_create) and opts are copied.  opts->check_every must be 0 or the
+ * server's; max_iter (>= 1) is rounded up to a multiple of it; autotune is the
+ * server's.  `out` is copied: its buffers (sized for k plans) must stay valid
+ * until the request's final status has been reported, and are written plan by
+ * plan as plans finish.  *ticket identifies the request.  The case must not be
+ * destroyed before its requests are final (queued requests of a destroyed case
+ * whose lane was released fail with LADMM_E_STATE). */
+int ladmm_submit(ladmm_server *s, ladmm_case *c, int32_t k, const ladmm_weights *w,
+                 const uint64_t *ld_mask, const ladmm_opts *opts, ladmm_result *out,
+                 uint64_t *ticket);
+/* Non-blocking status: LADMM_PENDING while plans remain, else the final status
+ * (LADMM_OK, LADMM_E_CANCELLED or the error that stopped the request).
+ * *plans_done (optional) = plans retired so far.  The first call that reports a
+ * final status releases the ticket; later calls return LADMM_E_STATE. */
+int ladmm_poll(ladmm_server *s, uint64_t ticket, int32_t *plans_done);
+/* Block until the request is final (timeout_us < 0: no limit), then as
+ * ladmm_poll; LADMM_PENDING on timeout.  One waiter per ticket. */
+int ladmm_wait(ladmm_server *s, uint64_t ticket, int64_t timeout_us);
+/* Ask for a request to stop: its queued plans are dropped and its running
+ * plans are freed at the next chunk boundary; its final status becomes
+ * LADMM_E_CANCELLED (plans already retired keep their results).  LADMM_OK
+ * also when the request is already final. */
+int ladmm_cancel(ladmm_server *s, uint64_t ticket);
+int ladmm_server_get_stats(ladmm_server *s, ladmm_server_stats *out);
+
 /* Message for the last error returned on this thread ("" if none). */
 const char *ladmm_last_error(void);
 /* Library version string. */

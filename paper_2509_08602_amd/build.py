@@ -67,7 +67,8 @@ def build(verbose: bool = False) -> str:
         if verbose and errs.strip():
             print(errs, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", *objs, "-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-Wl,--no-undefined", *objs,
+           "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)

@@ -24,12 +24,9 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ladmm.h"
-#include "kernels.h"
+#include "state.h"
 
-using namespace ladmm;
-
-namespace {
+namespace ladmm {
 
 thread_local std::string g_err;
 
@@ -37,28 +34,6 @@ int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
 }
-
-#define HIPC(call)                                                                   \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(LADMM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
-
-}  // namespace
-
-struct ladmm_ctx {
-  int device = 0;
-  size_t budget = 0;
-  size_t used = 0;
-  int refs = 0;              // live cases
-  bool destroyed = false;    // destroy requested while cases were alive
-  std::mutex mu;
-};
-
-namespace {
 
 // Device allocation charged to a context's HBM budget.
 int ctx_alloc(ladmm_ctx *ctx, void **p, size_t bytes, size_t *charged) {
@@ -86,6 +61,12 @@ void ctx_release(ladmm_ctx *ctx, size_t bytes) {
   ctx->used -= std::min(bytes, ctx->used);
 }
 
+}  // namespace ladmm
+
+using namespace ladmm;
+
+namespace ladmm {
+
 void ctx_ref(ladmm_ctx *ctx) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->refs++;
@@ -102,79 +83,9 @@ void ctx_unref(ladmm_ctx *ctx) {
   if (last) delete ctx;
 }
 
-}  // namespace
+}  // namespace ladmm
 
-struct ladmm_case {
-  ladmm_ctx *ctx = nullptr;
-  int precision = LADMM_F64;
-  int N = 0, Np = 0, n_iso = 0, S = 8, C = 3, n_t = 0, ntp = 0, n_sec = 0, mAp = 0, G = 0;
-  double beta = 1.0, cs = 0.0;
-  int row_normalize = 1;
-  SmallLayout L{};
-  void *D = nullptr;         // Np x ntp, scaled point block of A' (precision T)
-  void *sig = nullptr;       // Np (T)
-  int32_t *grp = nullptr;    // Np
-  int32_t *is_ld = nullptr;  // G + 1
-  int32_t *is_oar = nullptr; // G + 1
-  double *E = nullptr;       // mAp
-  double *gvec = nullptr;    // ntp
-  double *Smat = nullptr;    // mAp x mAp
-  double *Sinv = nullptr;    // mAp x mAp
-  std::vector<ladmm_group> groups;
-  std::vector<int32_t> hgrp;
-  std::vector<int64_t> counts;
-  std::vector<double> hE;
-  std::vector<void *> allocs;
-  size_t bytes = 0;
-  float setup_ms = 0.f;
-  int nchunk1 = 1, nchunk2 = 1;
-  int refs = 0;              // live batches
-  bool destroyed = false;    // destroy requested while batches were alive
-  std::vector<std::pair<int, std::pair<int, int>>> tuned;   // kp -> (GEMM1, GEMM2) tiles
-};
-
-struct ladmm_batch {
-  ladmm_case *c = nullptr;
-  int k = 0, kp = 0, mask_words = 0;
-  hipStream_t stream = nullptr;
-  void *q = nullptr;          // Np x kp (T): q = z1 + y1 of the dose points
-  void *W = nullptr;          // Np x kp (T): W = z1 - y1, input of the next GEMM1
-  double *qs = nullptr;       // n_sec x kp
-  double *q2 = nullptr;       // mAp x kp
-  void *utab = nullptr;       // (G + 1) x kp (T)
-  uint64_t *mask = nullptr;   // kp x mask_words
-  double *invrho = nullptr, *bbot = nullptr, *wbot = nullptr;
-  int32_t *active = nullptr;
-  void *P1 = nullptr;
-  double *r = nullptr, *P2 = nullptr, *v = nullptr;
-  void *vT = nullptr, *that = nullptr;
-  double *admm_stats = nullptr, *post_stats = nullptr, *obj_stats = nullptr, *fin = nullptr;
-  int admm_blocks = 0, post_blocks = 0, obj_blocks = 0;
-  std::vector<void *> allocs;
-  size_t bytes = 0;
-  std::vector<ladmm_weights> w;
-  std::vector<double> rho;
-  std::vector<int32_t> h_active, status, iters;
-  std::vector<double> rec;    // k x kFinal, per-plan statistics at the last check
-  double *h_fin = nullptr;    // pinned kp x kFinal
-  ladmm_opts opts{};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  double iterate_ms = 0.0;
-  int64_t plan_iters = 0;
-  int iters_run = 0;
-  // tile configurations of the two dose-matrix products (autotuned)
-  int cfg1 = 0, cfg2 = 0;
-  bool tuned = false;
-  // per-kernel event timing
-  bool profiling = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind;      // kind of each recorded pair
-  size_t ev_used = 0;            // events handed out in the current chunk
-  double kms[LADMM_N_KERNEL_CLASSES] = {};
-  int64_t kcount[LADMM_N_KERNEL_CLASSES] = {};
-};
-
-namespace {
+namespace ladmm {
 
 int case_alloc(ladmm_case *c, void **p, size_t bytes) {
   int rc = ctx_alloc(c->ctx, p, bytes, &c->bytes);
@@ -485,7 +396,15 @@ void case_free(ladmm_case *c) {
   ctx_unref(ctx);
 }
 
-// Drop a batch's reference; frees a case whose destroy call came first.
+// Take a reference on a live case (LADMM_E_STATE once destroy was called).
+int case_ref(ladmm_case *c) {
+  std::lock_guard<std::mutex> lk(c->ctx->mu);
+  if (c->destroyed) return fail(LADMM_E_STATE, "case has been destroyed");
+  c->refs++;
+  return LADMM_OK;
+}
+
+// Drop a reference; frees a case whose destroy call came first.
 void case_unref(ladmm_case *c) {
   bool last;
   {
@@ -586,12 +505,12 @@ int upload_tables(ladmm_batch *b, const uint64_t *ld_mask) {
 }
 
 int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const uint64_t *ld_mask,
-                      const double *rho, const ladmm_opts *opts, ladmm_batch **out) {
-  if (!c || !w || !opts || !out) return fail(LADMM_E_INVALID, "null argument");
+                      const double *rho, const ladmm_opts *opts, ladmm_batch **out, bool slots) {
+  if (!c || (!w && !slots) || !opts || !out) return fail(LADMM_E_INVALID, "null argument");
   if (k < 1) return fail(LADMM_E_INVALID, "k must be >= 1");
   if (opts->max_iter < 0 || opts->check_every < 1)
     return fail(LADMM_E_INVALID, "max_iter must be >= 0 and check_every >= 1");
-  for (int j = 0; j < k; ++j) {
+  for (int j = 0; j < k && !slots; ++j) {
     const ladmm_weights &x = w[j];
     if (!(x.w_bot > 0) || !std::isfinite(x.w_bot))
       return fail(LADMM_E_INVALID, "plan " + std::to_string(j) + ": w_bot must be > 0");
@@ -601,27 +520,32 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
     if (rho && (!(rho[j] > 0) || !std::isfinite(rho[j])))
       return fail(LADMM_E_INVALID, "plan " + std::to_string(j) + ": rho must be > 0");
   }
-  if (!rho && (!(opts->rho0 > 0) || !(opts->w0_bot > 0)))
+  if (!slots && !rho && (!(opts->rho0 > 0) || !(opts->w0_bot > 0)))
     return fail(LADMM_E_INVALID, "rho0 and w0_bot must be > 0");
 
-  if (c->destroyed) return fail(LADMM_E_STATE, "case has been destroyed");
+  {
+    int rc = case_ref(c);
+    if (rc) return rc;
+  }
   ladmm_batch *b = new ladmm_batch();
   b->c = c;
-  {
-    std::lock_guard<std::mutex> lk(c->ctx->mu);
-    c->refs++;
-  }
-  b->k = k;
   b->kp = round_up(k, 32);
+  b->k = slots ? b->kp : k;
+  k = b->k;
   b->opts = *opts;
-  b->w.assign(w, w + k);
+  if (slots)
+    b->w.assign(k, ladmm_weights{0.0, 0.0, 0.0, 1.0});
+  else
+    b->w.assign(w, w + k);
   b->rho.resize(k);
   for (int j = 0; j < k; ++j)
-    b->rho[j] = rho ? rho[j] : opts->rho0 * std::sqrt(opts->w0_bot / w[j].w_bot);
+    b->rho[j] = slots ? 1.0 : rho ? rho[j] : opts->rho0 * std::sqrt(opts->w0_bot / w[j].w_bot);
   b->h_active.assign(b->kp, 0);
-  for (int j = 0; j < k; ++j) b->h_active[j] = 1;
-  b->status.assign(k, LADMM_PLAN_RUNNING);
+  for (int j = 0; j < k && !slots; ++j) b->h_active[j] = 1;
+  b->status.assign(k, slots ? LADMM_PLAN_CONVERGED : LADMM_PLAN_RUNNING);
   b->iters.assign(k, 0);
+  b->start.assign(k, 0);
+  b->rule.assign(k, StopRule{opts->max_iter, opts->tol_gap, opts->tol_pri, opts->tol_dual});
   b->rec.assign((size_t)k * kFinal, NAN);
   b->mask_words = (c->Np + 63) / 64;
 
@@ -654,7 +578,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)c->n_sec * kp * sizeof(double))); b->qs = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->q2 = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)(c->G + 1) * kp * Tsz)); b->utab = p;
-  if (ld_mask) {
+  if (ld_mask || slots) {
     B_RC(batch_alloc(b, &p, (size_t)kp * b->mask_words * sizeof(uint64_t)));
     b->mask = (uint64_t *)p;
   }
@@ -670,8 +594,8 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->that = p;
   // statistics partials: one per row block of GEMM2, sized for the smallest
   // row block of any tile configuration (the autotuner may pick it)
-  const int max_row_blocks = c->Np / kNnMinRows;
-  b->admm_blocks = b->obj_blocks = c->Np / gemm_nn_block_rows(b->cfg2, c->Np, kp);
+  const int max_row_blocks = c->Np / kNnStatRows;
+  b->admm_blocks = b->obj_blocks = c->Np / kNnStatRows;
   b->post_blocks = post_blocks(c->L);
   B_RC(batch_alloc(b, &p, (size_t)max_row_blocks * kAdmmStats * kp * sizeof(double))); b->admm_stats = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)b->post_blocks * kAdmmStats * kp * sizeof(double))); b->post_stats = (double *)p;
@@ -683,7 +607,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_HIP(hipMemsetAsync(b->qs, 0, (size_t)c->n_sec * kp * sizeof(double), b->stream));
   B_HIP(hipMemsetAsync(b->q2, 0, (size_t)c->mAp * kp * sizeof(double), b->stream));
   B_HIP(hipStreamSynchronize(b->stream));
-  B_RC(upload_tables(b, ld_mask));
+  if (!slots) B_RC(upload_tables(b, ld_mask));
 #undef B_RC
 #undef B_HIP
   *out = b;
@@ -781,11 +705,8 @@ int iterate_any(ladmm_batch *b, bool stats) {
   return b->c->precision == LADMM_F64 ? iterate_once<double>(b, stats) : iterate_once<float>(b, stats);
 }
 
-// Number of GEMM2 row blocks (statistics partials) for the chosen configuration.
-void set_row_blocks(ladmm_batch *b) {
-  const int rows = gemm_nn_block_rows(b->cfg2, b->c->Np, b->kp);
-  b->admm_blocks = b->obj_blocks = b->c->Np / rows;
-}
+// Number of GEMM2 statistics partials (one per 64-row block, every configuration).
+void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np / kNnStatRows; }
 
 // Pick the fastest tile configuration of each dose-matrix product for this
 // case and plan count: a few timed launches of every valid configuration on the
@@ -847,21 +768,17 @@ int autotune(ladmm_batch *b) {
   return LADMM_OK;
 }
 
-// Run n iterations (the last one with statistics), update the host records and,
-// if `decide`, freeze plans that meet the stopping test.
-int run_chunk(ladmm_batch *b, int n, bool decide) {
-  if (n <= 0) return LADMM_OK;
-  if (!b->tuned) {
-    if (b->opts.autotune) {
-      int rc = b->c->precision == LADMM_F64 ? autotune<double>(b) : autotune<float>(b);
-      if (rc) return rc;
-    } else {
-      b->tuned = true;
-      set_row_blocks(b);
-    }
-  }
-  int n_active = 0;
-  for (int j = 0; j < b->k; ++j) n_active += b->h_active[j] != 0;
+int prepare_batch(ladmm_batch *b) {
+  if (b->tuned) return LADMM_OK;
+  if (b->opts.autotune) return b->c->precision == LADMM_F64 ? autotune<double>(b) : autotune<float>(b);
+  b->tuned = true;
+  set_row_blocks(b);
+  return LADMM_OK;
+}
+
+int chunk_launch(ladmm_batch *b, int n) {
+  b->chunk_active = 0;
+  for (int j = 0; j < b->k; ++j) b->chunk_active += b->h_active[j] != 0;
   HIPC(hipEventRecord(b->ev0, b->stream));
   for (int i = 0; i < n; ++i) {
     int rc = iterate_any(b, i == n - 1);
@@ -870,6 +787,10 @@ int run_chunk(ladmm_batch *b, int n, bool decide) {
   HIPC(hipEventRecord(b->ev1, b->stream));
   HIPC(hipMemcpyAsync(b->h_fin, b->fin, (size_t)b->kp * kFinal * sizeof(double),
                       hipMemcpyDeviceToHost, b->stream));
+  return LADMM_OK;
+}
+
+int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed_out) {
   HIPC(hipStreamSynchronize(b->stream));
   {
     int rc = prof_collect(b);
@@ -878,14 +799,14 @@ int run_chunk(ladmm_batch *b, int n, bool decide) {
   float ms = 0.f;
   HIPC(hipEventElapsedTime(&ms, b->ev0, b->ev1));
   b->iterate_ms += ms;
-  b->plan_iters += (int64_t)n * n_active;
+  b->plan_iters += (int64_t)n * b->chunk_active;
   b->iters_run += n;
   bool changed = false;
   for (int j = 0; j < b->k; ++j) {
     if (!b->h_active[j]) continue;
     const double *f = b->h_fin + (size_t)j * kFinal;
     std::memcpy(&b->rec[(size_t)j * kFinal], f, kFinal * sizeof(double));
-    b->iters[j] = b->iters_run;
+    b->iters[j] = b->iters_run - b->start[j];
     bool bad = false;
     for (int q = 0; q < kFinal; ++q) bad |= !std::isfinite(f[q]);
     if (bad) {
@@ -894,13 +815,33 @@ int run_chunk(ladmm_batch *b, int n, bool decide) {
       changed = true;
       continue;
     }
-    if (decide && b->opts.tol_gap > 0 && f[2] <= b->opts.tol_gap && f[3] <= b->opts.tol_pri &&
-        f[4] <= b->opts.tol_dual) {
+    if (!decide) continue;
+    const StopRule &r = b->rule[j];
+    if (r.tol_gap > 0 && f[2] <= r.tol_gap && f[3] <= r.tol_pri && f[4] <= r.tol_dual) {
       b->status[j] = LADMM_PLAN_CONVERGED;
+      b->h_active[j] = 0;
+      changed = true;
+    } else if (b->iters[j] >= r.max_iter) {
+      b->status[j] = LADMM_PLAN_MAX_ITER;
       b->h_active[j] = 0;
       changed = true;
     }
   }
+  if (changed_out) *changed_out = changed;
+  return LADMM_OK;
+}
+
+// Run n iterations (the last one with statistics), update the host records and,
+// if `decide`, freeze plans that meet their stopping rule.
+int run_chunk(ladmm_batch *b, int n, bool decide) {
+  if (n <= 0) return LADMM_OK;
+  int rc = prepare_batch(b);
+  if (rc) return rc;
+  rc = chunk_launch(b, n);
+  if (rc) return rc;
+  bool changed = false;
+  rc = chunk_complete(b, n, decide, &changed);
+  if (rc) return rc;
   if (changed)
     HIPC(hipMemcpy(b->active, b->h_active.data(), b->kp * sizeof(int32_t), hipMemcpyHostToDevice));
   return LADMM_OK;
@@ -922,6 +863,18 @@ int run_impl(ladmm_batch *b) {
   return LADMM_OK;
 }
 
+void bot_from_t(const ladmm_case *c, const double *t, double *bot) {
+  for (int i = 0; i < c->n_iso; ++i) {
+    double best = 0.0;
+    for (int s = 0; s < c->S; ++s) {
+      double sec = 0.0;
+      for (int cc = 0; cc < c->C; ++cc) sec += t[(i * c->S + s) * c->C + cc];
+      best = std::max(best, sec);
+    }
+    bot[i] = c->cs * best;
+  }
+}
+
 int results_impl(ladmm_batch *b, ladmm_result *out) {
   if (!out) return fail(LADMM_E_INVALID, "null result");
   ladmm_case *c = b->c;
@@ -938,18 +891,8 @@ int results_impl(ladmm_batch *b, ladmm_result *out) {
     hipFree(dt);
     if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("extract: ") + hipGetErrorString(e));
     if (out->t) std::memcpy(out->t, ht.data(), ht.size() * sizeof(double));
-    if (out->bot) {
-      for (int j = 0; j < k; ++j)
-        for (int i = 0; i < c->n_iso; ++i) {
-          double best = 0.0;
-          for (int s = 0; s < c->S; ++s) {
-            double sec = 0.0;
-            for (int cc = 0; cc < c->C; ++cc) sec += ht[(size_t)j * c->n_t + (i * c->S + s) * c->C + cc];
-            best = std::max(best, sec);
-          }
-          out->bot[(size_t)j * c->n_iso + i] = c->cs * best;
-        }
-    }
+    if (out->bot)
+      for (int j = 0; j < k; ++j) bot_from_t(c, &ht[(size_t)j * c->n_t], out->bot + (size_t)j * c->n_iso);
   }
   for (int j = 0; j < k; ++j) {
     const double *f = &b->rec[(size_t)j * kFinal];
@@ -964,7 +907,7 @@ int results_impl(ladmm_batch *b, ladmm_result *out) {
   return LADMM_OK;
 }
 
-}  // namespace
+}  // namespace ladmm
 
 // ---------------------------------------------------------------------------
 // exported entry points

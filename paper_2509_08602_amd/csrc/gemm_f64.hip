@@ -17,11 +17,6 @@ bool gemm_nn_cfg_ok(int cfg, int M, int N) {
   return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
 }
 
-int gemm_nn_block_rows(int cfg, int M, int N) {
-  if (!gemm_nn_cfg_ok(cfg, M, N)) cfg = 0;
-  return kNnCfgs[cfg].bm;
-}
-
 template hipError_t gemm_tn<double>(hipStream_t, const double *, int, const double *, int,
                                     double *, int, int, int, int, int, const PointTable<double> *,
                                     int);

@@ -272,12 +272,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
   // operand tiles; the statistics reduction reuses the same LDS after the K loop
   constexpr size_t kBytesA = sizeof(T) * 2 * BM * (BK + PADA);
   constexpr size_t kBytesB = sizeof(T) * 2 * BK * (BN + PADB);
-  constexpr size_t kBytesR = sizeof(double) * WM * NST * BN;
+  static_assert(BM % 64 == 0, "statistics partials are per 64-row block");
+  constexpr int T16 = BM / 16;   // 16-row tiles of the workgroup
+  constexpr size_t kBytesR = sizeof(double) * T16 * NST * BN;
   constexpr size_t kBytes = (kBytesA + kBytesB > kBytesR) ? kBytesA + kBytesB : kBytesR;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   auto sA = reinterpret_cast<T (*)[BM][BK + PADA]>(smem);
   auto sB = reinterpret_cast<T (*)[BK][BN + PADB]>(smem + kBytesA);
-  auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
+  auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);   // [16-row tile][stat][column]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -367,12 +369,17 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
     return;
   }
 
-  // per-column partial statistics of this lane
-  double st[TN][NST];
+  // Statistics: every lane sums its 4 rows of a 16-row tile, the 4 lanes of a
+  // column are combined by two shuffles, and the four 16-row tiles of each
+  // 64-row block are summed as (t0 + t1) + (t2 + t3).  The partial of a 64-row
+  // block is therefore the same for every tile configuration.
+  double st[TM][TN][NST];
 #pragma unroll
-  for (int tn = 0; tn < TN; ++tn)
+  for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-    for (int q = 0; q < NST; ++q) st[tn][q] = 0.0;
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int q = 0; q < NST; ++q) st[tm][tn][q] = 0.0;
 
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
@@ -389,10 +396,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
         if (EPI == EPI_OBJ) {
           // s = sign * dose / threshold at this point for shot times t / E
           if (ea.pt.is_oar[g]) {
-            st[tn][1] = fmax(st[tn][1], (double)(-s));
+            st[tm][tn][1] = fmax(st[tm][tn][1], (double)(-s));
           } else {
             const double h = fmax(0.0, (double)sg - (double)s);
-            st[tn][0] += (double)u * h;
+            st[tm][tn][0] = fma((double)u, h, st[tm][tn][0]);
           }
         } else {
           T *qp = ea.q + (size_t)m * ea.ldq + n;
@@ -410,40 +417,45 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
             const double zn = (double)clip0u(qn, u);
             const double yn = (double)qn - zn;
             const double x = (double)qn - yo;
-            st[tn][0] += (yn - yo) * (yn - yo);     // (x - z')^2
-            st[tn][1] += x * x;
-            st[tn][2] += zn * zn;
-            st[tn][3] += (zn - (double)z) * (zn - (double)z);
-            st[tn][4] += yn * yn;
-            st[tn][5] += -(double)sg * zn;           // c' z1
+            const double dxz = yn - yo, dz = zn - (double)z;
+            // explicit fused multiply-adds: the compiler's contraction choices
+            // may differ between configurations, these may not
+            st[tm][tn][0] = fma(dxz, dxz, st[tm][tn][0]);   // (x - z')^2
+            st[tm][tn][1] = fma(x, x, st[tm][tn][1]);
+            st[tm][tn][2] = fma(zn, zn, st[tm][tn][2]);
+            st[tm][tn][3] = fma(dz, dz, st[tm][tn][3]);
+            st[tm][tn][4] = fma(yn, yn, st[tm][tn][4]);
+            st[tm][tn][5] = fma(-(double)sg, zn, st[tm][tn][5]);   // c' z1
           }
         }
       }
     }
   if (EPI == EPI_ADMM) return;
 
-  // reduce over lanes with the same column (l, l+16, l+32, l+48), then waves
+  // per 16-row tile: combine the lanes of a column (l, l+16, l+32, l+48)
 #pragma unroll
-  for (int tn = 0; tn < TN; ++tn)
+  for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-    for (int q = 0; q < NST; ++q) {
-      double v = st[tn][q];
-      if (EPI == EPI_OBJ && q == 1) {
-        v = fmax(v, __shfl_xor(v, 16));
-        v = fmax(v, __shfl_xor(v, 32));
-      } else {
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
+    for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+      for (int q = 0; q < NST; ++q) {
+        double v = st[tm][tn][q];
+        if (EPI == EPI_OBJ && q == 1) {
+          v = fmax(v, __shfl_xor(v, 16));
+          v = fmax(v, __shfl_xor(v, 32));
+        } else {
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+        }
+        if (lane < 16) sred[wm * TM + tm][q][wn * TN * 16 + tn * 16 + lane] = v;
       }
-      if (lane < 16) sred[wm][q][wn * TN * 16 + tn * 16 + lane] = v;
-    }
   __syncthreads();
-  for (int e = tid; e < NST * BN; e += NT) {
-    const int q = e / BN, c = e % BN;
-    double v = sred[0][q][c];
-#pragma unroll
-    for (int w = 1; w < WM; ++w) v = (EPI == EPI_OBJ && q == 1) ? fmax(v, sred[w][q][c]) : v + sred[w][q][c];
-    ea.stats[((size_t)blockIdx.x * NST + q) * ea.nstat_cols + n0 + c] = v;
+  for (int e = tid; e < (BM / 64) * NST * BN; e += NT) {
+    const int b = e / (NST * BN), q = (e / BN) % NST, c = e % BN;
+    const double t0 = sred[4 * b][q][c], t1 = sred[4 * b + 1][q][c];
+    const double t2 = sred[4 * b + 2][q][c], t3 = sred[4 * b + 3][q][c];
+    const double v = (EPI == EPI_OBJ && q == 1) ? fmax(fmax(t0, t1), fmax(t2, t3)) : (t0 + t1) + (t2 + t3);
+    ea.stats[((size_t)(blockIdx.x * (BM / 64) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
   }
 }
 

@@ -37,10 +37,10 @@ struct PointTable {
 constexpr int kGemmCfgs = 4;
 bool gemm_tn_cfg_ok(int cfg, int M, int N);
 bool gemm_nn_cfg_ok(int cfg, int M, int N);
-// Rows per workgroup of the point-row product in configuration cfg: the
-// statistics epilogues write one partial per workgroup row block, M / rows.
-int gemm_nn_block_rows(int cfg, int M, int N);
-constexpr int kNnMinRows = 64;   // smallest row block of any configuration
+// The statistics epilogues of the point-row product write one partial per
+// 64-row block (M / 64 of them) whatever the configuration, summed in a fixed
+// order, so the statistics do not depend on the configuration either.
+constexpr int kNnStatRows = 64;
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
                    int M, int N, int K, int nchunk, const PointTable<T> *pro, int cfg = 0);
@@ -155,5 +155,10 @@ hipError_t export_points(hipStream_t s, const T *q, int ldq, const PointTable<T>
                          double *z, double *y);
 template <typename T>
 hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const double *z, const double *y);
+
+// Zero the columns j of a (rows x ld, row-major) whose flag[j] is nonzero:
+// the start of a fresh plan in a reused column.
+template <typename T>
+hipError_t zero_columns(hipStream_t s, T *a, size_t rows, int ld, const int32_t *flag);
 
 }  // namespace ladmm

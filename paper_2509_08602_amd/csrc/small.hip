@@ -16,6 +16,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ladmm {
 
 // ---------------------------------------------------------------------------
@@ -646,5 +648,25 @@ template hipError_t export_points<float>(hipStream_t, const float *, int, const 
 template hipError_t export_points<double>(hipStream_t, const double *, int, const PointTable<double> &, int, int, double *, double *);
 template hipError_t import_points<float>(hipStream_t, float *, int, int, int, const double *, const double *);
 template hipError_t import_points<double>(hipStream_t, double *, int, int, int, const double *, const double *);
+
+// a[r][j] = 0 for every row r < rows and column j < ld with flag[j] != 0.
+template <typename T>
+__global__ void k_zero_columns(T *__restrict__ a, size_t rows, int ld, const int32_t *__restrict__ flag) {
+  const size_t total = rows * (size_t)ld;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x)
+    if (flag[e % ld]) a[e] = T(0);
+}
+
+template <typename T>
+hipError_t zero_columns(hipStream_t s, T *a, size_t rows, int ld, const int32_t *flag) {
+  if (rows == 0 || ld <= 0) return hipSuccess;
+  const size_t total = rows * (size_t)ld;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL((k_zero_columns<T>), dim3(blocks), dim3(256), 0, s, a, rows, ld, flag);
+  return hipGetLastError();
+}
+template hipError_t zero_columns<float>(hipStream_t, float *, size_t, int, const int32_t *);
+template hipError_t zero_columns<double>(hipStream_t, double *, size_t, int, const int32_t *);
 
 }  // namespace ladmm

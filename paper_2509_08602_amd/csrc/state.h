@@ -1,0 +1,152 @@
+// Internal state of the library's handles (not part of the C ABI).
+//
+// A context owns a device and an HBM budget; a case owns the resident dose
+// block, the Schur complement inverse and the point tables; a batch owns k plan
+// columns (padded to kp) of iterates and per-plan tables.  The serving engine
+// keeps one batch per resident case whose columns are reused as slots.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ladmm.h"
+#include "kernels.h"
+
+namespace ladmm {
+
+// Message of the last error on the calling thread (ladmm_last_error).
+extern thread_local std::string g_err;
+int fail(int code, const std::string &msg);
+
+#define HIPC(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::ladmm::fail(LADMM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Stopping rule of one plan column: converged at a check where rel_gap,
+// r_pri and r_dual are within their tolerances (tol_gap <= 0: never), and
+// stopped at max_iter iterations of its own.
+struct StopRule {
+  int32_t max_iter;
+  double tol_gap, tol_pri, tol_dual;
+};
+
+}  // namespace ladmm
+
+struct ladmm_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  int refs = 0;              // live cases
+  bool destroyed = false;    // destroy requested while cases were alive
+  std::mutex mu;
+};
+
+struct ladmm_case {
+  ladmm_ctx *ctx = nullptr;
+  int precision = LADMM_F64;
+  int N = 0, Np = 0, n_iso = 0, S = 8, C = 3, n_t = 0, ntp = 0, n_sec = 0, mAp = 0, G = 0;
+  double beta = 1.0, cs = 0.0;
+  int row_normalize = 1;
+  ladmm::SmallLayout L{};
+  void *D = nullptr;         // Np x ntp, scaled point block of A' (precision T)
+  void *sig = nullptr;       // Np (T)
+  int32_t *grp = nullptr;    // Np
+  int32_t *is_ld = nullptr;  // G + 1
+  int32_t *is_oar = nullptr; // G + 1
+  double *E = nullptr;       // mAp
+  double *gvec = nullptr;    // ntp
+  double *Smat = nullptr;    // mAp x mAp
+  double *Sinv = nullptr;    // mAp x mAp
+  std::vector<ladmm_group> groups;
+  std::vector<int32_t> hgrp;
+  std::vector<int64_t> counts;
+  std::vector<double> hE;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  float setup_ms = 0.f;
+  int nchunk1 = 1, nchunk2 = 1;
+  int refs = 0;              // live batches
+  bool destroyed = false;    // destroy requested while batches were alive
+  std::vector<std::pair<int, std::pair<int, int>>> tuned;   // kp -> (GEMM1, GEMM2) tiles
+};
+
+struct ladmm_batch {
+  ladmm_case *c = nullptr;
+  int k = 0, kp = 0, mask_words = 0;
+  hipStream_t stream = nullptr;
+  void *q = nullptr;          // Np x kp (T): q = z1 + y1 of the dose points
+  void *W = nullptr;          // Np x kp (T): W = z1 - y1, input of the next GEMM1
+  double *qs = nullptr;       // n_sec x kp
+  double *q2 = nullptr;       // mAp x kp
+  void *utab = nullptr;       // (G + 1) x kp (T)
+  uint64_t *mask = nullptr;   // kp x mask_words
+  double *invrho = nullptr, *bbot = nullptr, *wbot = nullptr;
+  int32_t *active = nullptr;
+  void *P1 = nullptr;
+  double *r = nullptr, *P2 = nullptr, *v = nullptr;
+  void *vT = nullptr, *that = nullptr;
+  double *admm_stats = nullptr, *post_stats = nullptr, *obj_stats = nullptr, *fin = nullptr;
+  int admm_blocks = 0, post_blocks = 0, obj_blocks = 0;
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  std::vector<ladmm_weights> w;
+  std::vector<double> rho;
+  std::vector<int32_t> h_active, status, iters;
+  std::vector<int32_t> start;   // per plan: iters_run when the plan (re)started
+  std::vector<ladmm::StopRule> rule;   // per plan stopping rule
+  std::vector<double> rec;    // k x kFinal, per-plan statistics at the last check
+  double *h_fin = nullptr;    // pinned kp x kFinal
+  ladmm_opts opts{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double iterate_ms = 0.0;
+  int64_t plan_iters = 0;
+  int iters_run = 0;
+  int chunk_active = 0;       // active plans of the chunk in flight
+  // tile configurations of the two dose-matrix products (autotuned)
+  int cfg1 = 0, cfg2 = 0;
+  bool tuned = false;
+  // per-kernel event timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;      // kind of each recorded pair
+  size_t ev_used = 0;            // events handed out in the current chunk
+  double kms[LADMM_N_KERNEL_CLASSES] = {};
+  int64_t kcount[LADMM_N_KERNEL_CLASSES] = {};
+};
+
+namespace ladmm {
+
+int ctx_alloc(ladmm_ctx *ctx, void **p, size_t bytes, size_t *charged);
+void ctx_release(ladmm_ctx *ctx, size_t bytes);
+// Case references held by batches and queued requests; the last one frees a
+// destroyed case.
+int case_ref(ladmm_case *c);
+void case_unref(ladmm_case *c);
+int batch_alloc(ladmm_batch *b, void **p, size_t bytes);
+// slots = true: every column starts inactive, with a device LD mask, and the
+// per-plan tables are left for the caller to fill (the weights are ignored).
+int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const uint64_t *ld_mask,
+                      const double *rho, const ladmm_opts *opts, ladmm_batch **out,
+                      bool slots = false);
+int destroy_batch_impl(ladmm_batch *b);
+SmallArgs small_args(const ladmm_batch *b);
+// Tile configurations of the two dose-matrix products (autotuned or default).
+int prepare_batch(ladmm_batch *b);
+// Enqueue n iterations (the last with statistics) and the read-back of the
+// statistics on the batch's stream; returns without waiting.
+int chunk_launch(ladmm_batch *b, int n);
+// Wait for the chunk, update per-plan records, and with `decide` apply each
+// plan's stopping rule.  Frozen plans get h_active = 0; *changed reports any.
+int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed);
+// tau_i = (phi_cal/D_T) max_s sum_c t_isc for one plan's shot times.
+void bot_from_t(const ladmm_case *c, const double *t, double *bot);
+
+}  // namespace ladmm

@@ -10,6 +10,7 @@ import atexit
 import ctypes as C
 import dataclasses
 import os
+import weakref
 
 import numpy as np
 
@@ -71,15 +72,36 @@ class _Result(C.Structure):
                 ("plan_status", _IP)]
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("check_every", C.c_int32), ("max_lanes", C.c_int32),
+                ("autotune", C.c_int32)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("failed", C.c_int64), ("plans_completed", C.c_int64),
+                ("plan_iterations", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("mean_ms", C.c_double), ("busy_ms", C.c_double),
+                ("lanes", C.c_int32), ("busy_slots", C.c_int32)]
+
+
 _lib = None
 _EXITING = False
+_SERVERS = weakref.WeakSet()
 
 
 @atexit.register
 def _at_exit():
-    # Handles still alive at interpreter exit are left to the process teardown:
-    # calling into the HIP runtime from finalizers after this point is unsafe.
+    # Servers are stopped first (their worker threads call the HIP runtime).
+    # Other handles still alive at interpreter exit are left to the process
+    # teardown: calling into the HIP runtime from finalizers after this point is
+    # unsafe.
     global _EXITING
+    for s in list(_SERVERS):
+        try:
+            s.close()
+        except Exception:
+            pass
     _EXITING = True
 
 # name -> (restype, argtypes)
@@ -117,6 +139,15 @@ _SIGS = {
                                  C.POINTER(_Opts), C.POINTER(_Pass2), C.c_void_p,
                                  C.POINTER(_Result), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  _DP]),
+    "ladmm_server_create": (C.c_int, [C.c_void_p, C.POINTER(_ServerOpts), C.POINTER(C.c_void_p)]),
+    "ladmm_server_destroy": (C.c_int, [C.c_void_p]),
+    "ladmm_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(_Weights),
+                               C.POINTER(C.c_uint64), C.POINTER(_Opts), C.POINTER(_Result),
+                               C.POINTER(C.c_uint64)]),
+    "ladmm_poll": (C.c_int, [C.c_void_p, C.c_uint64, _IP]),
+    "ladmm_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64]),
+    "ladmm_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ladmm_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(_ServerStats)]),
     "ladmm_last_error": (C.c_char_p, []),
     "ladmm_version": (C.c_char_p, []),
 }
@@ -458,3 +489,101 @@ def select_ld_points(ctx: Context, volumes, n_ld, seed: int):
         C.byref(nP), masks.ctypes.data_as(C.POINTER(C.c_uint64))))
     npts = nP.value
     return P[:npts], masks[:k], unpack(masks[:k], npts) if k else np.zeros((0, 0), bool)
+
+
+class Ticket:
+    """A request queued on a Server; owns the result arrays the library writes."""
+
+    def __init__(self, server, case, weights, ld_mask, opts):
+        self.server, self.case = server, case
+        self._w, self.k = _weights(weights)
+        self._mask = _mask_words(ld_mask, case.n_points)
+        self.out, self._r = _result_buffers(self.k, case.n_t, case.n_iso)
+        self.status = PENDING
+        self.id = C.c_uint64()
+        mp = self._mask.ctypes.data_as(C.POINTER(C.c_uint64)) if self._mask is not None else None
+        _check(library().ladmm_submit(server._h, case._h, self.k, self._w, mp,
+                                      C.byref((opts or Options()).c()), C.byref(self._r),
+                                      C.byref(self.id)))
+
+    def _final(self, rc):
+        if rc != PENDING:
+            self.status = rc
+            self.server._done(self)
+        return rc
+
+    def poll(self):
+        """(status, plans_done); status is PENDING until the request is final."""
+        if self.status != PENDING:
+            return self.status, self.k
+        n = C.c_int32()
+        rc = library().ladmm_poll(self.server._h, self.id, C.byref(n))
+        if rc < 0 and rc != E_CANCELLED:
+            self._final(rc)
+            raise LadmmError(rc, library().ladmm_last_error().decode())
+        return self._final(rc), n.value
+
+    def wait(self, timeout: float | None = None):
+        """Block until final (or timeout seconds); returns the status."""
+        if self.status != PENDING:
+            return self.status
+        us = -1 if timeout is None else int(timeout * 1e6)
+        rc = library().ladmm_wait(self.server._h, self.id, us)
+        if rc < 0 and rc != E_CANCELLED:
+            self._final(rc)
+            raise LadmmError(rc, library().ladmm_last_error().decode())
+        return self._final(rc)
+
+    def cancel(self):
+        if self.status == PENDING:
+            _check(library().ladmm_cancel(self.server._h, self.id))
+
+    def result(self):
+        """Per-plan results (dict of arrays); waits for the request first."""
+        if self.wait() != OK:
+            raise LadmmError(self.status, "request did not complete")
+        return self.out
+
+
+class Server:
+    """Continuous-batching server (ladmm_server_*): requests of k plans on resident cases."""
+
+    def __init__(self, ctx: Context, slots: int = 96, check_every: int = 50, max_lanes: int = 0,
+                 autotune: bool = True):
+        self.ctx = ctx
+        self.check_every = int(check_every)
+        self._h = C.c_void_p()
+        self._live = {}
+        o = _ServerOpts(int(slots), int(check_every), int(max_lanes), 1 if autotune else 0)
+        _check(library().ladmm_server_create(ctx._h, C.byref(o), C.byref(self._h)))
+        _SERVERS.add(self)
+
+    def submit(self, case: Case, weights, ld_mask=None, opts: Options | None = None) -> Ticket:
+        t = Ticket(self, case, weights, ld_mask, opts)
+        self._live[t.id.value] = t   # keeps the buffers alive until final
+        return t
+
+    def _done(self, t):
+        self._live.pop(t.id.value, None)
+
+    def stats(self):
+        s = _ServerStats()
+        _check(library().ladmm_server_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            library().ladmm_server_destroy(self._h)
+            self._h = C.c_void_p()
+            for t in self._live.values():
+                if t.status == PENDING:
+                    t.status = E_CANCELLED
+            self._live.clear()
+
+    def __del__(self):
+        if _EXITING:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

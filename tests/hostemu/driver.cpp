@@ -43,11 +43,11 @@ int main(int argc, char **argv) {
   const std::string dir = argv[1];
   std::ifstream meta(dir + "/meta.txt");
   int N, n_iso, S, C, G, precision, k, iters, use_mask, n_vols, n_vox, band_vox, solve_iters;
-  int tile1 = -1, tile2 = -1, run_two_pass = 0;
+  int tile1 = -1, tile2 = -1, run_two_pass = 0, serve = 0;
   double rho0, w0, D_T, phi_cal, d_ld, delta;
   unsigned long long seed;
   meta >> N >> n_iso >> S >> C >> G >> precision >> k >> iters >> rho0 >> w0 >> D_T >> phi_cal >>
-      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2 >> run_two_pass;
+      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2 >> run_two_pass >> serve;
   const int n_t = n_iso * S * C, m_A = n_t + n_iso, n_A = N + n_iso * S;
   auto dose = load<double>(dir + "/dose.f64", (size_t)N * n_t);
   auto grp = load<int32_t>(dir + "/group.i32", N);
@@ -81,6 +81,7 @@ int main(int argc, char **argv) {
   ladmm_opts o{};
   o.max_iter = 1000; o.check_every = 7; o.tol_gap = 0.0; o.tol_pri = 1; o.tol_dual = 1;
   o.rho0 = rho0; o.w0_bot = w0; o.autotune = 1;
+  if (!serve) {
   ladmm_batch *b = nullptr;
   CHECK(ladmm_batch_create(cs, k, w.data(), use_mask ? mask.data() : nullptr, nullptr, &o, &b));
   if (tile1 >= 0) CHECK(ladmm_batch_set_tiles(b, tile1, tile2));
@@ -115,6 +116,7 @@ int main(int argc, char **argv) {
     so.max_iter = solve_iters; so.check_every = 5; so.tol_gap = 1e-6; so.tol_pri = 1e-6; so.tol_dual = 1e-6;
     CHECK(ladmm_solve_batch(cs, k, w.data(), use_mask ? mask.data() : nullptr, &so, &r));
   }
+  }
   if (n_vols > 0) {
     const int Wv = (n_vox + 63) / 64;
     auto vols = load<uint64_t>(dir + "/vols.u64", (size_t)n_vols * Wv);
@@ -148,6 +150,68 @@ int main(int argc, char **argv) {
     save(dir + "/tp_t2.f64", t2.data(), t2.size());
     save(dir + "/tp_f2.f64", f2.data(), f2.size());
     save(dir + "/tp_P.i64", P.data(), (size_t)n2[0]);
+  }
+  if (serve) {
+    // Continuous batching on 32 slots: a long request cancelled at once, then
+    // request A (k - 6 plans, 2K iterations) and B (6 plans, K iterations), so
+    // B's later plans start in slots freed by its earlier ones.  The same plans
+    // are also solved alone with ladmm_solve_batch for a bitwise comparison.
+    const int K = 2, kA = k - 6, kB = 6;
+    ladmm_server_opts sopt{32, K, 0, 0};
+    ladmm_server *sv = nullptr;
+    CHECK(ladmm_server_create(ctx, &sopt, &sv));
+    ladmm_opts ro = o;
+    ro.check_every = 0; ro.tol_gap = 0.0; ro.autotune = 0;
+    ladmm_opts oc = ro, oa = ro, ob = ro;
+    oc.max_iter = 1000; oa.max_iter = 2 * K; ob.max_iter = K;
+    std::vector<double> tc(n_t);
+    ladmm_result rc{tc.data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint64_t tkc = 0, tka = 0, tkb = 0;
+    CHECK(ladmm_submit(sv, cs, 1, &w[0], nullptr, &oc, &rc, &tkc));
+    CHECK(ladmm_cancel(sv, tkc));
+    const int nreq = 2;
+    const int kk[nreq] = {kA, kB}, off[nreq] = {0, kA};
+    std::vector<double> tt[nreq], ff[nreq], rt[nreq], rf[nreq];
+    std::vector<int32_t> ii[nreq], ss[nreq], ri[nreq], rs[nreq];
+    ladmm_result rr[nreq], ref[nreq];
+    for (int q = 0; q < nreq; ++q) {
+      tt[q].resize((size_t)kk[q] * n_t); ff[q].resize(kk[q]); ii[q].resize(kk[q]); ss[q].resize(kk[q]);
+      rt[q].resize((size_t)kk[q] * n_t); rf[q].resize(kk[q]); ri[q].resize(kk[q]); rs[q].resize(kk[q]);
+      rr[q] = ladmm_result{tt[q].data(), nullptr, ff[q].data(), nullptr, nullptr, nullptr, nullptr,
+                           ii[q].data(), ss[q].data()};
+      ref[q] = ladmm_result{rt[q].data(), nullptr, rf[q].data(), nullptr, nullptr, nullptr, nullptr,
+                            ri[q].data(), rs[q].data()};
+    }
+    const uint64_t *ma = use_mask ? mask.data() : nullptr;
+    const uint64_t *mb = use_mask ? mask.data() + (size_t)kA * W : nullptr;
+    CHECK(ladmm_submit(sv, cs, kA, &w[0], ma, &oa, &rr[0], &tka));
+    CHECK(ladmm_submit(sv, cs, kB, &w[kA], mb, &ob, &rr[1], &tkb));
+    if (ladmm_wait(sv, tkc, -1) != LADMM_E_CANCELLED) { fprintf(stderr, "cancel failed\n"); return 4; }
+    CHECK(ladmm_wait(sv, tka, -1));
+    CHECK(ladmm_wait(sv, tkb, -1));
+    if (ladmm_poll(sv, tka, nullptr) != LADMM_E_STATE) { fprintf(stderr, "ticket not released\n"); return 4; }
+    ladmm_server_stats st{};
+    CHECK(ladmm_server_get_stats(sv, &st));
+    if (st.completed != 2 || st.cancelled != 1 || st.plans_completed != k) {
+      fprintf(stderr, "stats %lld %lld %lld\n", (long long)st.completed, (long long)st.cancelled,
+              (long long)st.plans_completed);
+      return 4;
+    }
+    CHECK(ladmm_server_destroy(sv));
+    ladmm_opts sa = oa, sb = ob;
+    sa.check_every = K; sb.check_every = K;
+    CHECK(ladmm_solve_batch(cs, kA, &w[0], ma, &sa, &ref[0]));
+    CHECK(ladmm_solve_batch(cs, kB, &w[kA], mb, &sb, &ref[1]));
+    for (int q = 0; q < nreq; ++q) {
+      const std::string tag = q == 0 ? "A" : "B";
+      save(dir + "/serve_t" + tag + ".f64", tt[q].data(), tt[q].size());
+      save(dir + "/serve_f" + tag + ".f64", ff[q].data(), ff[q].size());
+      save(dir + "/serve_i" + tag + ".i32", ii[q].data(), ii[q].size());
+      save(dir + "/alone_t" + tag + ".f64", rt[q].data(), rt[q].size());
+      save(dir + "/alone_f" + tag + ".f64", rf[q].data(), rf[q].size());
+      save(dir + "/alone_i" + tag + ".i32", ri[q].data(), ri[q].size());
+    }
+    (void)off;
   }
   CHECK(ladmm_destroy_case(cs));
   CHECK(ladmm_ctx_destroy(ctx));

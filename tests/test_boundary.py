@@ -37,14 +37,43 @@ def test_library_exports_every_declared_symbol():
     assert set(ladmm._SIGS) <= set(declared_functions())
 
 
-def test_binding_struct_layouts_match_header():
-    """Sizes of the C structs as the binding lays them out (x86-64 SysV ABI)."""
+STRUCTS = {  # C struct name -> binding class name
+    "ladmm_group": "_Group", "ladmm_weights": "_Weights", "ladmm_opts": "_Opts",
+    "ladmm_result": "_Result", "ladmm_case_desc": "_CaseDesc", "ladmm_pass2_desc": "_Pass2",
+    "ladmm_server_opts": "_ServerOpts", "ladmm_server_stats": "_ServerStats",
+}
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Size and field offsets of every C struct, as gcc lays out the header,
+    equal those of the binding's ctypes structures."""
+    import shutil
+    import subprocess
     from paper_2509_08602_amd import ladmm
-    assert ctypes.sizeof(ladmm._Group) == 24
-    assert ctypes.sizeof(ladmm._Weights) == 32
-    assert ctypes.sizeof(ladmm._Opts) == 56
-    assert ctypes.sizeof(ladmm._Result) == 72
-    assert ctypes.sizeof(ladmm._CaseDesc) == 88
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ladmm.h"', "int main(void) {"]
+    for cname, pname in STRUCTS.items():
+        cls = getattr(ladmm, pname)
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            s, f, v = line.split()
+            got[(s, f)] = int(v)
+    for cname, pname in STRUCTS.items():
+        cls = getattr(ladmm, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_mask_packing():

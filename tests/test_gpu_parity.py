@@ -264,3 +264,28 @@ def test_solve_c1_f32_sampled_exact(ctx, c1):
     F_orc = olp.planning_objective(c1, w, res["t"].T)[0]
     assert rel_err(res["objective"], F_orc) < 1e-5
     assert all(v < 1e-3 for v in rel.values()), rel
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tile_configurations_give_identical_results(ctx, c0, precision):
+    """Every pair of tile configurations of the two dose-matrix products yields
+    the same iterates and the same statistics, bit for bit (the configurations
+    split the work but never reorder a floating-point sum)."""
+    say("tile independence", precision)
+    w = cases.config_weights(0)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    opts = ladmm.Options(max_iter=100, check_every=50, tol_gap=0.0, rho0=1000.0,
+                         w0_bot=cases.W0_BOT, autotune=False)
+    ref = None
+    for c1 in range(4):
+        for c2 in range(4):
+            b = ladmm.Batch(dc, w, opts=opts)
+            b.set_tiles(c1, c2)
+            b.run()
+            res = b.results()
+            b.close()
+            if ref is None:
+                ref = res
+                continue
+            for key, val in res.items():
+                assert np.array_equal(val, ref[key]), (c1, c2, key)

@@ -1,0 +1,176 @@
+"""GPU serving: continuous batching through ladmm_submit / poll / wait / cancel.
+
+A plan's arithmetic does not depend on the other plans in its lane, on its slot
+or on when it was admitted, so every plan served in a mix must equal, bitwise,
+the same request solved alone by ladmm_solve_batch (same options, max_iter a
+multiple of check_every).  The alone results are themselves pinned to the
+oracle by the parity tests; here the served objectives are also checked against
+the exact LP optimum F* of the stored golden values.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from synth import cases
+from oracle import lp as olp
+
+pytestmark = pytest.mark.gpu
+
+ladmm = pytest.importorskip("paper_2509_08602_amd.ladmm")
+
+
+def read_fstar(config):
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_golden
+    return make_golden.read(config)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return ladmm.Context(0)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    return cases.make_case(0)
+
+
+@pytest.fixture(scope="module")
+def mini():
+    spec = cases.mini_spec(n_iso=3, sectors=8, collimators=3, radius=4.0, n_ring=400, n_ld=300)
+    return cases.build_case(spec, 11)
+
+
+def opts(max_iter, tol=1e-4, K=50):
+    return ladmm.Options(max_iter=max_iter, check_every=K, tol_gap=tol, tol_pri=tol, tol_dual=tol,
+                         rho0=1000.0, w0_bot=cases.W0_BOT, autotune=False)
+
+
+def same(a, b):
+    for key in ("t", "bot", "objective", "dual_obj", "rel_gap", "r_pri", "r_dual", "iters",
+                "plan_status"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_served_plans_equal_plans_solved_alone(ctx, c0, mini):
+    """Requests on two cases, sizes 1 to 9, submitted while others run, on 32
+    slots per lane; the probe request R arrives mid-stream."""
+    say("serve mix c0 + mini, f64")
+    d0 = ladmm.Case.from_case(ctx, c0, "f64")
+    dm = ladmm.Case.from_case(ctx, mini, "f64")
+    w0 = cases.config_weights(0)
+    wr = cases.random_weights(40, 3)
+    o, oR = opts(1000), opts(8000)
+    alone_R = ladmm.solve_batch(d0, w0, opts=oR)
+    alone_m = [ladmm.solve_batch(dm, wr[i:i + 8], opts=o) for i in range(0, 40, 8)]
+    alone_1 = ladmm.solve_batch(d0, wr[5:6], opts=o)
+    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=False)
+    tm = [srv.submit(dm, wr[i:i + 8], opts=o) for i in range(0, 24, 8)]
+    t1 = srv.submit(d0, wr[5:6], opts=o)
+    time.sleep(0.05)
+    tR = srv.submit(d0, w0, opts=oR)
+    tm += [srv.submit(dm, wr[i:i + 8], opts=o) for i in range(24, 40, 8)]
+    same(tR.result(), alone_R)
+    same(t1.result(), alone_1)
+    for t, ref in zip(tm, alone_m):
+        same(t.result(), ref)
+    st = srv.stats()
+    say("stats", st)
+    assert st["completed"] == 7 and st["failed"] == 0 and st["plans_completed"] == 9 + 1 + 40
+    assert st["p50_ms"] > 0 and st["p99_ms"] >= st["p50_ms"]
+    srv.close()
+    fstar = read_fstar(0)
+    F = tR.out["objective"]
+    for j, fs in fstar.items():
+        assert abs(F[j] - fs) <= 1e-3 * abs(fs) + 1e-9, (j, F[j], fs)
+
+
+def test_slot_reuse_and_masks_match_alone(ctx, mini):
+    """More plans than slots (plans start in freed slots), with LD masks, FP32."""
+    say("serve slot reuse mini f32")
+    dm = ladmm.Case.from_case(ctx, mini, "f32")
+    k = 70
+    w = cases.random_weights(k, 6)
+    types = mini.point_types()
+    rng = np.random.default_rng(2)
+    mask = np.zeros((k, mini.n_points), bool)
+    ld = np.nonzero(types == cases.LD)[0]
+    for j in range(k):
+        mask[j, ld[rng.random(ld.size) < 0.7]] = True
+    reqs = [(0, 30, 200), (30, 31, 400), (31, 70, 100)]
+    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=True)
+    tickets = [srv.submit(dm, w[a:b], ld_mask=mask[a:b], opts=opts(m, tol=0.0)) for a, b, m in reqs]
+    for (a, b, m), t in zip(reqs, tickets):
+        ref = ladmm.solve_batch(dm, w[a:b], ld_mask=mask[a:b], opts=opts(m, tol=0.0))
+        got = t.result()
+        same(got, ref)
+        assert np.all(got["iters"] == m)
+        F = olp.planning_objective(mini, w[a:b], got["t"].T, mask[a:b])[0]
+        assert np.max(np.abs(got["objective"] - F) / np.maximum(np.abs(F), 1e-12)) < 1e-5
+    srv.close()
+
+
+def test_cancel_poll_and_release(ctx, mini):
+    say("serve cancel")
+    dm = ladmm.Case.from_case(ctx, mini, "f64")
+    w = cases.random_weights(4, 8)
+    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=False)
+    long = srv.submit(dm, w, opts=opts(200000, tol=0.0))
+    short = srv.submit(dm, w[:2], opts=opts(100, tol=0.0))
+    assert short.wait() == ladmm.OK
+    status, _ = long.poll()
+    assert status == ladmm.PENDING
+    long.cancel()
+    assert long.wait() == ladmm.E_CANCELLED
+    # the ticket was released by the report; the library now rejects it
+    rc = ladmm.library().ladmm_poll(srv._h, long.id, None)
+    assert rc == ladmm.E_STATE
+    ref = ladmm.solve_batch(dm, w[:2], opts=opts(100, tol=0.0))
+    same(short.out, ref)
+    st = srv.stats()
+    assert st["cancelled"] == 1 and st["completed"] == 1
+    with pytest.raises(ladmm.LadmmError):
+        srv.submit(dm, w, opts=ladmm.Options(max_iter=100, check_every=7))   # wrong check_every
+    srv.close()
+
+
+def test_hbm_budget_evicts_idle_lanes(ctx, mini, c0):
+    """A budget that holds both cases but one lane at a time: requests on the two
+    cases still all complete (lanes are released and re-created), unchanged."""
+    say("serve budget")
+    probe = ladmm.Context(0)
+    a = ladmm.Case.from_case(probe, mini, "f64")
+    b = ladmm.Case.from_case(probe, c0, "f64")
+    cases_bytes = probe.used_bytes
+    srv = ladmm.Server(probe, slots=32, check_every=50, autotune=False)
+    srv.submit(a, cases.random_weights(1, 1), opts=opts(50)).wait()
+    lane_a = probe.used_bytes - cases_bytes
+    srv.close()
+    srv = ladmm.Server(probe, slots=32, check_every=50, autotune=False)
+    srv.submit(b, cases.random_weights(1, 1), opts=opts(50)).wait()
+    lane_b = probe.used_bytes - cases_bytes
+    srv.close()
+    a.close(), b.close()
+    budget = cases_bytes + max(lane_a, lane_b) + min(lane_a, lane_b) // 2
+    small = ladmm.Context(0, hbm_budget=budget)
+    ca = ladmm.Case.from_case(small, mini, "f64")
+    cb = ladmm.Case.from_case(small, c0, "f64")
+    w = cases.random_weights(6, 12)
+    o = opts(300)
+    srv = ladmm.Server(small, slots=32, check_every=50, autotune=False)
+    ts = [srv.submit(ca, w[:3], opts=o), srv.submit(cb, w[3:], opts=o), srv.submit(ca, w[3:], opts=o)]
+    res = [t.result() for t in ts]
+    assert small.used_bytes <= budget
+    st = srv.stats()
+    assert st["completed"] == 3 and st["lanes"] <= 1
+    srv.close()
+    same(res[0], ladmm.solve_batch(ca, w[:3], opts=o))
+    same(res[1], ladmm.solve_batch(cb, w[3:], opts=o))
+    same(res[2], ladmm.solve_batch(ca, w[3:], opts=o))

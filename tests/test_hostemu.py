@@ -67,7 +67,7 @@ def driver():
 
 def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, seed=0,
                  vox=None, d_ld=0.0, delta=1.0, solve_iters=0, rho0=1000.0, tiles=(-1, -1),
-                 two_pass=False):
+                 two_pass=False, serve=False):
     os.makedirs(d, exist_ok=True)
     k = w.shape[0]
     n_vols = 0 if vols is None else vols.shape[0]
@@ -78,7 +78,7 @@ def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, 
                 f"{len(case.groups)} {0 if precision == 'f64' else 1} {k} {iters} {rho0!r} "
                 f"{cases.W0_BOT!r} {case.prescription_mean!r} {case.phi_cal!r} "
                 f"{0 if mask is None else 1} {n_vols} {n_vox} {seed} {band} {d_ld!r} {delta!r} "
-                f"{solve_iters} {tiles[0]} {tiles[1]} {int(two_pass)}\n")
+                f"{solve_iters} {tiles[0]} {tiles[1]} {int(two_pass)} {int(serve)}\n")
     np.ascontiguousarray(case.dose, np.float64).tofile(os.path.join(d, "dose.f64"))
     np.ascontiguousarray(case.group, np.int32).tofile(os.path.join(d, "group.i32"))
     with open(os.path.join(d, "groups.txt"), "w") as f:
@@ -208,3 +208,35 @@ def test_emulated_two_pass(driver, tmp_path):
     t2 = rd(d, "tp_t2.f64", (k, n_t))
     F2 = olp.planning_objective(case2, w, t2.T, mask2)[0]
     assert rel_err(rd(d, "tp_f2.f64", (k,)), F2) < 1e-10
+
+
+def test_emulated_serving(driver, tmp_path):
+    """Continuous batching through ladmm_submit/wait/cancel: a cancelled request,
+    then two requests whose plans share 32 slots (later plans start in slots
+    freed by earlier ones).  Every plan's shot times, objective and iteration
+    count equal those of ladmm_solve_batch on its own request, bitwise, and the
+    objective is the oracle's F of the returned shot times."""
+    case = small_case(7)
+    k = 36
+    w = cases.random_weights(k, 9)
+    types = case.point_types()
+    rng = np.random.default_rng(4)
+    mask = np.zeros((k, case.n_points), bool)
+    ld = np.nonzero(types == cases.LD)[0]
+    for j in range(k):
+        mask[j, ld[rng.random(ld.size) < 0.5]] = True
+    d = str(tmp_path / "serve")
+    write_inputs(d, case, w, "f32", 1, mask=mask, tiles=(0, 0), serve=True)
+    run(driver, d)
+    n_t = case.n_t
+    for tag, sl, iters in (("A", slice(0, k - 6), 4), ("B", slice(k - 6, k), 2)):
+        kk = sl.stop - sl.start
+        t = rd(d, f"serve_t{tag}.f64", (kk, n_t))
+        assert np.array_equal(t, rd(d, f"alone_t{tag}.f64", (kk, n_t))), tag
+        f = rd(d, f"serve_f{tag}.f64", (kk,))
+        assert np.array_equal(f, rd(d, f"alone_f{tag}.f64", (kk,))), tag
+        it = np.fromfile(os.path.join(d, f"serve_i{tag}.i32"), np.int32)
+        assert it.tolist() == [iters] * kk
+        assert np.array_equal(it, np.fromfile(os.path.join(d, f"alone_i{tag}.i32"), np.int32))
+        F = olp.planning_objective(case, w[sl], t.T, mask[sl])[0]
+        assert rel_err(f, F) < 1e-5
