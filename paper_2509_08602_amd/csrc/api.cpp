@@ -142,6 +142,30 @@ int setup_precision(ladmm_case *c, const double *Dt, hipStream_t s) {
   return LADMM_OK;
 }
 
+// Number of row chunks of a split-K product over K rows whose output has
+// `tiles` tiles: the fewest chunks (of at least min_rows rows, boundaries on
+// 32-row multiples as the product places them) that give `rounds` or more
+// rounds of workgroups over the CUs with the last round nearly full.
+int balanced_chunks(int K, int tiles, int min_rows, int rounds_min) {
+  constexpr int kCUs = 256;
+  const int maxc = std::max(1, K / min_rows);
+  int best = maxc;
+  double best_eff = -1.0;
+  for (int n = 1; n <= maxc; ++n) {
+    const int kchunk = round_up((K + n - 1) / n, 32);
+    const int neff = (K + kchunk - 1) / kchunk;
+    const long W = (long)tiles * neff;
+    const long rounds = (W + kCUs - 1) / kCUs;
+    const double eff = (double)W / (double)(kCUs * rounds);
+    if (W >= rounds_min * kCUs - kCUs / 16 && eff >= 0.95) return neff;
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = neff;
+    }
+  }
+  return best;
+}
+
 int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out) {
   if (!ctx || !d || !out) return fail(LADMM_E_INVALID, "null argument");
   if (d->n_points < 1 || d->n_iso < 1 || d->n_sectors < 1 || d->n_collimators < 1)
@@ -207,8 +231,8 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   c->L = SmallLayout{c->n_t, c->ntp, c->n_iso, c->mAp, c->n_sec, c->S, c->C};
   // GEMM split factors depend on the case only, so a plan's arithmetic does
   // not depend on how many other plans share its batch.
-  c->nchunk1 = std::max(1, std::min((1024 + c->ntp / 64 - 1) / (c->ntp / 64), c->Np / 256));
-  c->nchunk2 = std::max(1, std::min(16, (512 + c->mAp / 64 - 1) / (c->mAp / 64)));
+  c->nchunk1 = balanced_chunks(c->Np, c->ntp / 64, 256, 4);
+  c->nchunk2 = balanced_chunks(c->mAp, c->mAp / 32, 64, 2);
 
   auto cleanup = [&](int rc) {
     for (void *p : c->allocs) hipFree(p);
@@ -661,7 +685,7 @@ int iterate_once(ladmm_batch *b, bool stats) {
                       kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
   PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
   PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
-                           c->nchunk2, nullptr)));
+                           c->nchunk2, nullptr, 1)));
   PROF(3, (vreduce<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (T *)b->vT)));
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
   EpiArgs<T> ea{};
@@ -705,7 +729,7 @@ int iterate_any(ladmm_batch *b, bool stats) {
   return b->c->precision == LADMM_F64 ? iterate_once<double>(b, stats) : iterate_once<float>(b, stats);
 }
 
-// Number of GEMM2 statistics partials (one per 64-row block, every configuration).
+// Number of GEMM2 statistics partials (one per 32-row block, every configuration).
 void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np / kNnStatRows; }
 
 // Pick the fastest tile configuration of each dose-matrix product for this

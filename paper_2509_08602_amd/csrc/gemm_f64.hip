@@ -13,8 +13,10 @@ bool gemm_tn_cfg_ok(int cfg, int M, int N) {
 bool gemm_nn_cfg_ok(int cfg, int M, int N) {
   if (cfg < 0 || cfg >= kGemmCfgs) return false;
   const NnCfg c = kNnCfgs[cfg];
-  const int BN = pick_bn(N);
-  return M % c.bm == 0 && c.bm % (16 * c.wm) == 0 && BN % (16 * c.wn) == 0;
+  const int BN = nn_bn(c, N);
+  const bool inst = BN == 16 || BN == 32 || BN == 48 || BN == 64 || BN == 96 || BN == 128;
+  return inst && N % BN == 0 && M % c.bm == 0 && c.bm % (16 * c.wm) == 0 &&
+         BN % (16 * c.wn) == 0 && (c.wn == 1 || BN % 32 == 0);
 }
 
 template hipError_t gemm_tn<double>(hipStream_t, const double *, int, const double *, int,

@@ -75,6 +75,13 @@ __device__ __forceinline__ T upper_of(const PointTable<T> &pt, int g, int p, int
 template <typename T>
 __device__ __forceinline__ T clip0u(T q, T u) { return fmin(fmax(q, T(0)), u); }
 
+// Padding (in elements) that makes a row of W + pad elements of T span 16 (mod
+// 32) LDS banks, so two half-wavefronts reading consecutive rows never collide.
+template <typename T, int W>
+constexpr int row_pad() {
+  return sizeof(T) == 4 ? ((16 - W) % 32 + 32) % 32 : ((8 - W) % 16 + 16) % 16;
+}
+
 // ---------------------------------------------------------------------------
 // P[z][m][n] = sum_{k in chunk z} A[k][m] * B'[k][n],  A: K x M, B: K x N
 // B' = B, or with the ADMM prologue B' = 2 clip(q, 0, u) - q  (z1 - y1).
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(const T *__restrict__ 
   constexpr int VN = V16<T>::n;
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
   static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
-  constexpr int PADA = (sizeof(T) == 4) ? 16 : 8, PADB = PADA;
+  constexpr int PADA = row_pad<T, BM>(), PADB = row_pad<T, BN>();
   constexpr int AV = BK * BM / VN, BV = BK * BN / VN;           // vectors per slice
   constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;  // per thread
   typedef typename V16<T>::V VT;
@@ -204,48 +211,50 @@ static int pick_bn(int N) {
   return 32;
 }
 
-// Tile configurations of the split-K product (row tile BM, wavefront grid WM x WN).
-struct TnCfg { int bm, wm, wn; };
-static const TnCfg kTnCfgs[kGemmCfgs] = {{64, 2, 2}, {32, 2, 2}, {64, 4, 2}, {64, 4, 1}};
+// Tile configurations of the split-K product: row tile BM, slice depth BK,
+// wavefront grid WM x WN; the column block is pick_bn(N).
+struct TnCfg { int bm, bk, wm, wn; };
+static const TnCfg kTnCfgs[kGemmCfgs] = {{64, 16, 2, 2}, {32, 16, 2, 2}, {64, 32, 4, 2}, {64, 16, 4, 2}};
 
 
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
                    int M, int N, int K, int nchunk, const PointTable<T> *pro, int cfg) {
-  constexpr int BK = 16;
   if (!gemm_tn_cfg_ok(cfg, M, N)) cfg = 0;
   if (!gemm_tn_cfg_ok(cfg, M, N) || N % 32 != 0 || nchunk < 1) return hipErrorInvalidValue;
   if (lda % V16<T>::n || ldb % V16<T>::n) return hipErrorInvalidValue;
+  // chunk boundaries are multiples of 32 rows whatever the slice depth, so the
+  // order of every sum is the same in every configuration
   int kchunk = (K + nchunk - 1) / nchunk;
-  kchunk = (kchunk + BK - 1) / BK * BK;
+  kchunk = (kchunk + 31) / 32 * 32;
   const size_t pstride = (size_t)M * ldp;
   PointTable<T> pt{};
   if (pro) pt = *pro;
   const int BN = pick_bn(N);
   const TnCfg c = kTnCfgs[cfg];
   dim3 grid(M / c.bm, N / BN, nchunk);
-#define TN_ONE(BMv, BNv, WMv, WNv)                                                            \
+#define TN_ONE(BMv, BNv, BKv, WMv, WNv)                                                       \
   do {                                                                                       \
     if (pro)                                                                                 \
-      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BK, WMv, WNv, true>), grid, dim3(64 * WMv * WNv), \
+      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BKv, WMv, WNv, true>), grid, dim3(64 * WMv * WNv), \
                          0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
     else                                                                                     \
-      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BK, WMv, WNv, false>), grid, dim3(64 * WMv * WNv), \
+      hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BKv, WMv, WNv, false>), grid, dim3(64 * WMv * WNv), \
                          0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
   } while (0)
-#define TN_BN(BMv, WMv, WNv)                                  \
+#define TN_BN(BMv, BKv, WMv, WNv)                                  \
   switch (BN) {                                               \
-    case 32: if (32 % (16 * WNv) == 0) TN_ONE(BMv, 32, WMv, WNv); break; \
-    case 64: TN_ONE(BMv, 64, WMv, WNv); break;                \
-    case 96: if (96 % (16 * WNv) == 0) TN_ONE(BMv, 96, WMv, WNv); break; \
-    case 128: TN_ONE(BMv, 128, WMv, WNv); break;              \
+    case 32: if (32 % (16 * WNv) == 0) TN_ONE(BMv, 32, BKv, WMv, WNv); break; \
+    case 64: TN_ONE(BMv, 64, BKv, WMv, WNv); break;                \
+    case 96: if (96 % (16 * WNv) == 0) TN_ONE(BMv, 96, BKv, WMv, WNv); break; \
+    case 128: TN_ONE(BMv, 128, BKv, WMv, WNv); break;              \
     default: return hipErrorInvalidValue;                     \
   }
   switch (cfg) {
-    case 0: TN_BN(64, 2, 2) break;
-    case 1: TN_BN(32, 2, 2) break;
-    case 2: TN_BN(64, 4, 2) break;
-    case 3: TN_BN(64, 4, 1) break;
+    case 0: TN_BN(64, 16, 2, 2) break;
+    case 1: TN_BN(32, 16, 2, 2) break;
+    case 2: TN_BN(64, 32, 4, 2) break;
+    case 3: TN_BN(64, 16, 4, 2) break;
   }
 #undef TN_BN
 #undef TN_ONE
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
   static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
   constexpr int PADA = (sizeof(T) == 4) ? 2 : 1;       // k-contiguous rows: stride = 2 mod 32 words
-  constexpr int PADB = (sizeof(T) == 4) ? 16 : 8;
+  constexpr int PADB = row_pad<T, BN>();
   constexpr int AV = BM * BK / VN, BV = BK * BN / VN;
   constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;
   constexpr int NST = (EPI == EPI_OBJ) ? kObjStats : kAdmmStats;
@@ -272,9 +281,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
   // operand tiles; the statistics reduction reuses the same LDS after the K loop
   constexpr size_t kBytesA = sizeof(T) * 2 * BM * (BK + PADA);
   constexpr size_t kBytesB = sizeof(T) * 2 * BK * (BN + PADB);
-  static_assert(BM % 64 == 0, "statistics partials are per 64-row block");
+  static_assert(BM % 32 == 0, "statistics partials are per 32-row block");
   constexpr int T16 = BM / 16;   // 16-row tiles of the workgroup
-  constexpr size_t kBytesR = sizeof(double) * T16 * NST * BN;
+  constexpr bool kStats = EPI == EPI_ADMM_STATS || EPI == EPI_OBJ;
+  constexpr size_t kBytesR = kStats ? sizeof(double) * T16 * NST * BN : 0;
   constexpr size_t kBytes = (kBytesA + kBytesB > kBytesR) ? kBytesA + kBytesB : kBytesR;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   auto sA = reinterpret_cast<T (*)[BM][BK + PADA]>(smem);
@@ -370,9 +380,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
   }
 
   // Statistics: every lane sums its 4 rows of a 16-row tile, the 4 lanes of a
-  // column are combined by two shuffles, and the four 16-row tiles of each
-  // 64-row block are summed as (t0 + t1) + (t2 + t3).  The partial of a 64-row
-  // block is therefore the same for every tile configuration.
+  // column are combined by two shuffles, and the two 16-row tiles of each
+  // 32-row block are added.  The partial of a 32-row block is therefore the
+  // same for every tile configuration.
   double st[TM][TN][NST];
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
@@ -450,18 +460,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
         if (lane < 16) sred[wm * TM + tm][q][wn * TN * 16 + tn * 16 + lane] = v;
       }
   __syncthreads();
-  for (int e = tid; e < (BM / 64) * NST * BN; e += NT) {
+  for (int e = tid; e < (BM / 32) * NST * BN; e += NT) {
     const int b = e / (NST * BN), q = (e / BN) % NST, c = e % BN;
-    const double t0 = sred[4 * b][q][c], t1 = sred[4 * b + 1][q][c];
-    const double t2 = sred[4 * b + 2][q][c], t3 = sred[4 * b + 3][q][c];
-    const double v = (EPI == EPI_OBJ && q == 1) ? fmax(fmax(t0, t1), fmax(t2, t3)) : (t0 + t1) + (t2 + t3);
-    ea.stats[((size_t)(blockIdx.x * (BM / 64) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
+    const double t0 = sred[2 * b][q][c], t1 = sred[2 * b + 1][q][c];
+    const double v = (EPI == EPI_OBJ && q == 1) ? fmax(t0, t1) : t0 + t1;
+    ea.stats[((size_t)(blockIdx.x * (BM / 32) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
   }
 }
 
-// Tile configurations of the point-row product (BM rows, wavefront grid WM x WN).
-struct NnCfg { int bm, wm, wn; };
-static const NnCfg kNnCfgs[kGemmCfgs] = {{128, 4, 1}, {64, 2, 2}, {128, 4, 2}, {64, 4, 2}};
+// Tile configurations of the point-row product: BM rows, a column block of
+// pick_bn(N) / bn_div columns (bn_div = 0: 32 columns), wavefront grid WM x WN.
+// Narrower column blocks give more workgroups (better balance over the CUs)
+// at the price of reading the row slab once per column block.
+struct NnCfg { int bm, bn_div, wm, wn; };
+static const NnCfg kNnCfgs[kGemmCfgs] = {{128, 1, 4, 1}, {64, 2, 4, 1}, {128, 0, 4, 1}, {64, 1, 4, 2}};
+
+static int nn_bn(const NnCfg &c, int N) { return c.bn_div == 0 ? 32 : pick_bn(N) / c.bn_div; }
 
 
 
@@ -472,8 +486,8 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
   if (!gemm_nn_cfg_ok(cfg, M, N)) cfg = 0;
   if (!gemm_nn_cfg_ok(cfg, M, N) || N % 32 != 0 || K % BK != 0) return hipErrorInvalidValue;
   if (lda % V16<T>::n || ldb % V16<T>::n) return hipErrorInvalidValue;
-  const int BN = pick_bn(N);
   const NnCfg c = kNnCfgs[cfg];
+  const int BN = nn_bn(c, N);
   const dim3 grid(M / c.bm, N / BN);
 #define NN_ONE(BMv, BNv, WMv, WNv, E)                                                          \
   hipLaunchKernelGGL((k_gemm_nn<T, BMv, BNv, BK, WMv, WNv, E>), grid, dim3(64 * WMv * WNv), 0, s, \
@@ -488,7 +502,9 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
   }
 #define NN_BN(BMv, WMv, WNv)                                              \
   switch (BN) {                                                          \
+    case 16: if (WNv == 1) { NN_E(BMv, 16, WMv, 1) } break;               \
     case 32: if (32 % (16 * WNv) == 0) { NN_E(BMv, 32, WMv, WNv) } break; \
+    case 48: if (WNv == 1) { NN_E(BMv, 48, WMv, 1) } break;               \
     case 64: { NN_E(BMv, 64, WMv, WNv) } break;                          \
     case 96: if (96 % (16 * WNv) == 0) { NN_E(BMv, 96, WMv, WNv) } break; \
     case 128: { NN_E(BMv, 128, WMv, WNv) } break;                        \
@@ -496,8 +512,8 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
   }
   switch (cfg) {
     case 0: NN_BN(128, 4, 1) break;
-    case 1: NN_BN(64, 2, 2) break;
-    case 2: NN_BN(128, 4, 2) break;
+    case 1: NN_BN(64, 4, 1) break;
+    case 2: NN_BN(128, 4, 1) break;
     case 3: NN_BN(64, 4, 2) break;
   }
 #undef NN_BN

@@ -38,9 +38,9 @@ constexpr int kGemmCfgs = 4;
 bool gemm_tn_cfg_ok(int cfg, int M, int N);
 bool gemm_nn_cfg_ok(int cfg, int M, int N);
 // The statistics epilogues of the point-row product write one partial per
-// 64-row block (M / 64 of them) whatever the configuration, summed in a fixed
+// 32-row block (M / 32 of them) whatever the configuration, summed in a fixed
 // order, so the statistics do not depend on the configuration either.
-constexpr int kNnStatRows = 64;
+constexpr int kNnStatRows = 32;
 template <typename T>
 hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P, int ldp,
                    int M, int N, int K, int nchunk, const PointTable<T> *pro, int cfg = 0);

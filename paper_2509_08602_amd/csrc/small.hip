@@ -336,6 +336,8 @@ __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int
   double out = 0.0;
   if (m < L.n_t) {
     double g = 0.0;
+    // the partials are independent loads: keep several in flight
+#pragma unroll 8
     for (int z = 0; z < nchunk; ++z) g += (double)P1[z * zstride + (size_t)m * kp + j];
     const int sec = m / L.C;
     const double qsv = qs[(size_t)sec * kp + j];
@@ -375,6 +377,7 @@ __global__ void k_vreduce(SmallArgs a, const double *__restrict__ P2, size_t zst
   if (m >= a.L.mAp || j >= a.kp) return;
   const size_t idx = (size_t)m * a.kp + j;
   double acc = 0.0;
+#pragma unroll 8
   for (int z = 0; z < nchunk; ++z) acc += P2[z * zstride + idx];
   v[idx] = acc;
   if (m < a.L.ntp) vT[idx] = (T)acc;
