@@ -51,8 +51,17 @@ typedef enum {
 
 /* Storage and arithmetic of the dose matrix and the dose-point iterates.  The
  * Schur complement, its factor and inverse, and the small per-row iterates are
- * always FP64. */
-typedef enum { LADMM_F64 = 0, LADMM_F32 = 1 } ladmm_precision;
+ * always FP64.
+ *   LADMM_F64:    FP64 dose block and iterates, FP64 MFMA.
+ *   LADMM_F32:    FP32 dose block and iterates, FP32 MFMA.
+ *   LADMM_BF16X3: the dose block and the plan-side operands of the two products
+ *                 (z1 - y1, the Schur solution, the shot times) as BF16 pairs
+ *                 hi = bf16(x), lo = bf16(x - hi); each product sums
+ *                 A_hi B_hi + A_hi B_lo + A_lo B_hi on the BF16 MFMA with FP32
+ *                 accumulation (about 2^-16 relative per product); iterates FP32.
+ *                 The dose block takes 8 bytes per entry (two pairs, one per
+ *                 product layout). */
+typedef enum { LADMM_F64 = 0, LADMM_F32 = 1, LADMM_BF16X3 = 2 } ladmm_precision;
 
 /* Dose-point group types (App. A subscripts TS, TI, R, LD, O). */
 typedef enum { LADMM_PT_TS = 0, LADMM_PT_TI = 1, LADMM_PT_RING = 2, LADMM_PT_LD = 3,

@@ -142,6 +142,22 @@ int setup_precision(ladmm_case *c, const double *Dt, hipStream_t s) {
   return LADMM_OK;
 }
 
+// D^ = Dt diag(E) as BF16 pairs in both layouts: point-major (for the
+// point-row products) and shot-major (for the split-K product).
+int setup_bf16(ladmm_case *c, const double *Dt, hipStream_t s) {
+  void *p = nullptr;
+  const size_t n = (size_t)c->Np * c->ntp;
+  int rc = case_alloc(c, &p, 4 * n * sizeof(uint16_t));
+  if (rc) return rc;
+  uint16_t *base = (uint16_t *)p;
+  c->Dh = base;
+  c->Dl = base + n;
+  c->DTh = base + 2 * n;
+  c->DTl = base + 3 * n;
+  HIPC(split_dose_bf16(s, Dt, c->E, c->Np, c->ntp, base, base + n, base + 2 * n, base + 3 * n));
+  return LADMM_OK;
+}
+
 // Number of row chunks of a split-K product over K rows whose output has
 // `tiles` tiles: the fewest chunks (of at least min_rows rows, boundaries on
 // 32-row multiples as the product places them) that give `rounds` or more
@@ -174,7 +190,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
     return fail(LADMM_E_INVALID, "dose, point_group and groups are required");
   if (!(d->prescription_mean > 0) || !(d->phi_cal > 0))
     return fail(LADMM_E_INVALID, "prescription_mean and phi_cal must be > 0");
-  if (d->precision != LADMM_F64 && d->precision != LADMM_F32)
+  if (d->precision != LADMM_F64 && d->precision != LADMM_F32 && d->precision != LADMM_BF16X3)
     return fail(LADMM_E_INVALID, "unknown precision");
   const int n_t = d->n_iso * d->n_sectors * d->n_collimators;
   for (int g = 0; g < d->n_groups; ++g) {
@@ -386,8 +402,10 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   // scaled dose block in the iteration precision: D^ = D~ diag(E)
   if (c->precision == LADMM_F64) {
     SETUP_RC(setup_precision<double>(c, Dt, s));
-  } else {
+  } else if (c->precision == LADMM_F32) {
     SETUP_RC(setup_precision<float>(c, Dt, s));
+  } else {
+    SETUP_RC(setup_bf16(c, Dt, s));
   }
   SETUP_HIP(hipEventRecord(e1, s));
   SETUP_HIP(hipStreamSynchronize(s));
@@ -725,8 +743,72 @@ int iterate_once(ladmm_batch *b, bool stats) {
   return LADMM_OK;
 }
 
+// Plan-major BF16 pairs stored in the space of a Np x kp (or ntp x kp) FP32
+// buffer: hi rows first, then lo rows.
+BfPair plan_pairs(void *buf, int kp, int len) {
+  const uint16_t *h = (const uint16_t *)buf;
+  return BfPair{h, h + (size_t)kp * len, len};
+}
+
+// One iteration with the BF16-pair products (same steps as iterate_once).
+int iterate_bf(ladmm_batch *b, bool stats) {
+  ladmm_case *c = b->c;
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
+  const BfPair W = plan_pairs(b->W, kp, c->Np), V = plan_pairs(b->vT, kp, c->ntp);
+  SmallArgs sa = small_args(b);
+  PROF(0, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+  PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+                           c->nchunk2, nullptr, 1)));
+  PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
+                      (uint16_t *)V.lo)));
+  PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
+  EpiArgs<float> ea{};
+  ea.q = (float *)b->q;
+  ea.ldq = kp;
+  ea.invrho = b->invrho;
+  ea.active = b->active;
+  ea.stats = b->admm_stats;
+  ea.nstat_cols = kp;
+  ea.pt = point_table<float>(b);
+  ea.wt_hi = (uint16_t *)W.hi;
+  ea.wt_lo = (uint16_t *)W.lo;
+  ea.ldwt = c->Np;
+  PROF(4, (gemm_bf_nn(s, stats ? EPI_ADMM_STATS : EPI_ADMM, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2)));
+  if (stats) {
+    const BfPair Tt = plan_pairs(b->that, kp, c->ntp);
+    PROF(6, (shot_scaled_bf(s, sa, b->q2, (uint16_t *)Tt.hi, (uint16_t *)Tt.lo)));
+    EpiArgs<float> eo = ea;
+    eo.stats = b->obj_stats;
+    PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, b->cfg2)));
+    FinalArgs fa;
+    fa.admm_stats = b->admm_stats;
+    fa.admm_blocks = b->admm_blocks;
+    fa.post_stats = b->post_stats;
+    fa.post_blocks = b->post_blocks;
+    fa.obj_stats = b->obj_stats;
+    fa.obj_blocks = b->obj_blocks;
+    fa.q2 = b->q2;
+    fa.E = c->E;
+    fa.invrho = b->invrho;
+    fa.wbot = b->wbot;
+    fa.L = c->L;
+    fa.cs = c->cs;
+    fa.kp = kp;
+    fa.out = b->fin;
+    PROF(7, (finalize(s, fa)));
+  }
+  return LADMM_OK;
+}
+
 int iterate_any(ladmm_batch *b, bool stats) {
-  return b->c->precision == LADMM_F64 ? iterate_once<double>(b, stats) : iterate_once<float>(b, stats);
+  switch (b->c->precision) {
+    case LADMM_F64: return iterate_once<double>(b, stats);
+    case LADMM_F32: return iterate_once<float>(b, stats);
+    default: return iterate_bf(b, stats);
+  }
 }
 
 // Number of GEMM2 statistics partials (one per 32-row block, every configuration).
@@ -737,6 +819,58 @@ void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np 
 // live batch (GEMM2 runs with its writes masked off).  Results are cached per
 // case and padded plan count.  The configurations change only the work split,
 // never the order of the sums, so the choice does not affect the iterates.
+// Whether tile configuration cfg suits the split-K (which = 0) or the
+// point-row (which = 1) product of this batch's shapes.
+bool cfg_ok(const ladmm_batch *b, int which, int cfg) {
+  const ladmm_case *c = b->c;
+  if (c->precision == LADMM_BF16X3)
+    return which == 0 ? gemm_bf_cfg_ok(cfg, c->ntp, b->kp) : gemm_bf_cfg_ok(cfg, c->Np, b->kp);
+  return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kp) : gemm_nn_cfg_ok(cfg, c->Np, b->kp);
+}
+
+// One launch of a dose-matrix product in configuration cfg (the point-row
+// product with its writes masked off by `noact`).
+template <typename T>
+hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact) {
+  ladmm_case *c = b->c;
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  if (c->precision == LADMM_BF16X3) {
+    const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
+    if (which == 0)
+      return gemm_bf_tn(s, DT, plan_pairs(b->W, kp, c->Np), (float *)b->P1, kp, c->ntp, kp, c->Np,
+                        c->nchunk1, 3, cfg);
+    EpiArgs<float> ea{};
+    ea.q = (float *)b->q;
+    ea.ldq = kp;
+    ea.invrho = b->invrho;
+    ea.active = noact;
+    ea.pt = point_table<float>(b);
+    ea.wt_hi = (uint16_t *)b->W;
+    ea.wt_lo = (uint16_t *)b->W + (size_t)kp * c->Np;
+    ea.ldwt = c->Np;
+    return gemm_bf_nn(s, EPI_ADMM, Dp, plan_pairs(b->vT, kp, c->ntp), c->Np, kp, c->ntp, ea, 3, cfg);
+  }
+  if (which == 0)
+    return gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1, kp, c->ntp, kp,
+                      c->Np, c->nchunk1, nullptr, cfg);
+  EpiArgs<T> ea{};
+  ea.q = (T *)b->q;
+  ea.w = (T *)b->W;
+  ea.ldq = kp;
+  ea.invrho = b->invrho;
+  ea.active = noact;
+  ea.pt = point_table<T>(b);
+  return gemm_nn<T>(s, EPI_ADMM, (const T *)c->D, c->ntp, (const T *)b->vT, kp, c->Np, kp, c->ntp,
+                    ea, cfg);
+}
+
+// Pick the fastest tile configuration of each dose-matrix product for this
+// case and plan count: a few timed launches of every valid configuration on the
+// live batch (the point-row product runs with its writes masked off).  Results
+// are cached per case and padded plan count.  The configurations change only
+// the work split, never the order of the sums, so the choice does not affect
+// the iterates.
 template <typename T>
 int autotune(ladmm_batch *b) {
   ladmm_case *c = b->c;
@@ -750,30 +884,17 @@ int autotune(ladmm_batch *b) {
     }
   hipStream_t s = b->stream;
   const int kp = b->kp;
-  PointTable<T> pt = point_table<T>(b);
   int32_t *noact = nullptr;
   HIPC(hipMalloc((void **)&noact, kp * sizeof(int32_t)));
   hipError_t e = hipMemsetAsync(noact, 0, kp * sizeof(int32_t), s);
-  EpiArgs<T> ea{};
-  ea.q = (T *)b->q;
-  ea.w = (T *)b->W;
-  ea.ldq = kp;
-  ea.invrho = b->invrho;
-  ea.active = noact;
-  ea.pt = pt;
   float best1 = 1e30f, best2 = 1e30f;
   for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
     for (int which = 0; which < 2 && e == hipSuccess; ++which) {
-      const bool ok = which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, kp) : gemm_nn_cfg_ok(cfg, c->Np, kp);
-      if (!ok) continue;
+      if (!cfg_ok(b, which, cfg)) continue;
       float tot = 0.f;
       for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
         e = hipEventRecord(b->ev0, s);
-        if (e == hipSuccess)
-          e = which == 0 ? gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1,
-                                      kp, c->ntp, kp, c->Np, c->nchunk1, nullptr, cfg)
-                         : gemm_nn<T>(s, EPI_ADMM, (const T *)c->D, c->ntp, (const T *)b->vT, kp,
-                                      c->Np, kp, c->ntp, ea, cfg);
+        if (e == hipSuccess) e = tune_launch<T>(b, which, cfg, noact);
         if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
         if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
         float ms = 0.f;
@@ -1114,9 +1235,12 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const
                              point_table<double>(b));
     } else {
       e = import_points<float>(b->stream, (float *)b->q, kp, N, k, dz, dy);
-      if (e == hipSuccess)
+      if (e == hipSuccess && c->precision == LADMM_F32)
         e = w_from_q<float>(b->stream, (const float *)b->q, (float *)b->W, c->Np, kp,
                             point_table<float>(b));
+      else if (e == hipSuccess)
+        e = w_from_q_bf(b->stream, (const float *)b->q, c->Np, kp, point_table<float>(b),
+                        (uint16_t *)b->W, (uint16_t *)b->W + (size_t)kp * c->Np);
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1166,8 +1290,8 @@ int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
   if (gemm1 < 0 || gemm1 >= kGemmCfgs || gemm2 < 0 || gemm2 >= kGemmCfgs)
     return fail(LADMM_E_INVALID, "tile configuration out of range");
-  b->cfg1 = gemm_tn_cfg_ok(gemm1, b->c->ntp, b->kp) ? gemm1 : 0;
-  b->cfg2 = gemm_nn_cfg_ok(gemm2, b->c->Np, b->kp) ? gemm2 : 0;
+  b->cfg1 = cfg_ok(b, 0, gemm1) ? gemm1 : 0;
+  b->cfg2 = cfg_ok(b, 1, gemm2) ? gemm2 : 0;
   b->tuned = true;
   set_row_blocks(b);
   return LADMM_OK;

@@ -59,6 +59,7 @@ struct EpiArgs {
   const int32_t *active;           // per plan
   double *stats; int nstat_cols;   // partial stats [blockIdx.x][stat][nstat_cols]
   PointTable<T> pt;
+  uint16_t *wt_hi, *wt_lo; int ldwt;   // BF16-pair products: W' = z1' - y1' as plans x points
 };
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb,
@@ -155,6 +156,34 @@ hipError_t export_points(hipStream_t s, const T *q, int ldq, const PointTable<T>
                          double *z, double *y);
 template <typename T>
 hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const double *z, const double *y);
+
+// ---- BF16-pair products --------------------------------------------------------
+// An FP32/FP64 operand x is carried as the pair hi = bf16(x), lo = bf16(x - hi)
+// (16 significant bits); both operands are stored row-major with the
+// reduction index contiguous (A: M x K rows, B: N x K rows).  A product sums
+// A_hi B_hi + A_hi B_lo (+ A_lo B_hi with terms = 3) on the BF16 MFMA with FP32
+// accumulation, in the same order for every tile configuration.
+struct BfPair { const uint16_t *hi, *lo; int ld; };
+bool gemm_bf_cfg_ok(int cfg, int M, int N);
+// P[z][m][n] = sum over rows k of chunk z of A[m][k] B[n][k]  (split-K partials, FP32)
+hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
+                      int nchunk, int terms, int cfg);
+// C = A B' with the ADMM / statistics / objective epilogues (W' written as pairs)
+hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
+                      const EpiArgs<float> &ea, int terms, int cfg);
+// D^ = Dt diag(E) as pairs, point-major (Np x ntp) and shot-major (ntp x Np).
+hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int Np, int ntp,
+                           uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl);
+// v_top and the scaled shot times as plan-major pairs (kp x ntp) for the products.
+hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
+                      double *v, uint16_t *vh, uint16_t *vl);
+hipError_t shot_scaled_bf(hipStream_t s, const SmallArgs &a, const double *q2, uint16_t *th,
+                          uint16_t *tl);
+// Zero rows j (hi and lo) of plan-major pairs (2 kp rows of len) with flag[j] != 0.
+hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const int32_t *flag);
+// W' pairs (kp x Np) from q after a state import.
+hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
+                       uint16_t *wh, uint16_t *wl);
 
 // Zero the columns j of a (rows x ld, row-major) whose flag[j] is nonzero:
 // the start of a fresh plan in a reused column.

@@ -197,9 +197,12 @@ int upload(Lane &L) {
     if (c->precision == LADMM_F64) {
       HIPC(zero_columns<double>(s, (double *)b->q, c->Np, kp, L.d_reset));
       HIPC(zero_columns<double>(s, (double *)b->W, c->Np, kp, L.d_reset));
-    } else {
+    } else if (c->precision == LADMM_F32) {
       HIPC(zero_columns<float>(s, (float *)b->q, c->Np, kp, L.d_reset));
       HIPC(zero_columns<float>(s, (float *)b->W, c->Np, kp, L.d_reset));
+    } else {   // W' is held as plan-major BF16 pairs
+      HIPC(zero_columns<float>(s, (float *)b->q, c->Np, kp, L.d_reset));
+      HIPC(zero_plan_rows_bf(s, (uint16_t *)b->W, kp, c->Np, L.d_reset));
     }
     HIPC(zero_columns<double>(s, b->qs, c->n_sec, kp, L.d_reset));
     HIPC(zero_columns<double>(s, b->q2, c->mAp, kp, L.d_reset));

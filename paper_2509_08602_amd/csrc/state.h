@@ -57,6 +57,8 @@ struct ladmm_case {
   int row_normalize = 1;
   ladmm::SmallLayout L{};
   void *D = nullptr;         // Np x ntp, scaled point block of A' (precision T)
+  // LADMM_BF16X3: the same block as BF16 pairs, point-major and shot-major
+  const uint16_t *Dh = nullptr, *Dl = nullptr, *DTh = nullptr, *DTl = nullptr;
   void *sig = nullptr;       // Np (T)
   int32_t *grp = nullptr;    // Np
   int32_t *is_ld = nullptr;  // G + 1

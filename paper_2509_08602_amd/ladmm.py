@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libladmm.so")
 
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_CANCELLED = -1, -2, -3, -4, -5, -6
-F64, F32 = 0, 1
+F64, F32, BF16X3 = 0, 1, 2
 PT_TS, PT_TI, PT_RING, PT_LD, PT_OAR = 0, 1, 2, 3, 4
 PLAN_CONVERGED, PLAN_MAX_ITER, PLAN_NUMERIC, PLAN_RUNNING = 0, 1, 2, 3
-PRECISIONS = {"f64": F64, "f32": F32}
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
 
 
 class LadmmError(RuntimeError):

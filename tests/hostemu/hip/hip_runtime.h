@@ -28,6 +28,8 @@ struct dim3 {
 };
 struct float4 { float x, y, z, w; };
 struct double2 { double x, y; };
+struct uint4 { unsigned x, y, z, w; };
+struct uint2 { unsigned x, y; };
 
 namespace hostemu {
 extern dim3 threadIdx_, blockIdx_, blockDim_, gridDim_;
@@ -102,6 +104,41 @@ inline hostemu_f4 __builtin_amdgcn_mfma_f32_16x16x4f32(float a, float b, hostemu
 }
 inline hostemu_d4 __builtin_amdgcn_mfma_f64_16x16x4f64(double a, double b, hostemu_d4 c, int, int, int) {
   return hostemu::mfma16<double, hostemu_d4, true>(a, b, c);
+}
+
+typedef __bf16 hostemu_bf8 __attribute__((ext_vector_type(8)));
+
+namespace hostemu {
+// D = A B + C for one 16x16x32 BF16 MFMA: lane l supplies A[l % 16][8 (l / 16) + e]
+// and B[8 (l / 16) + e][l % 16] (e = 0..7) and receives D[4 (l / 16) + r][l % 16].
+inline hostemu_f4 mfma16_bf16(hostemu_bf8 a, hostemu_bf8 b, hostemu_f4 c) {
+  struct Slot { float a[8], b[8]; };
+  Slot *mine = (Slot *)wave_slot(sizeof(Slot));
+  for (int e = 0; e < 8; ++e) {
+    mine->a[e] = (float)a[e];
+    mine->b[e] = (float)b[e];
+  }
+  barrier();
+  const int me = lane_id(), base = me & ~63, l = me & 63;
+  hostemu_f4 d = c;
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * (l >> 4) + r, col = l & 15;
+    float acc = d[r];
+    for (int k = 0; k < 32; ++k) {
+      const Slot *pa = (const Slot *)peer_slot(base + row + 16 * (k / 8));
+      const Slot *pb = (const Slot *)peer_slot(base + col + 16 * (k / 8));
+      acc += pa->a[k % 8] * pb->b[k % 8];
+    }
+    d[r] = acc;
+  }
+  barrier();
+  return d;
+}
+}  // namespace hostemu
+
+inline hostemu_f4 __builtin_amdgcn_mfma_f32_16x16x32_bf16(hostemu_bf8 a, hostemu_bf8 b, hostemu_f4 c,
+                                                          int, int, int) {
+  return hostemu::mfma16_bf16(a, b, c);
 }
 
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }

@@ -69,7 +69,8 @@ def test_setup_matches_oracle(ctx, c0):
     assert rel_err(Si @ S_ref, np.eye(S.shape[0])) < 1e-10
 
 
-@pytest.mark.parametrize("precision,tol1,tol50", [("f64", 1e-12, 1e-9), ("f32", 2e-5, 5e-4)])
+@pytest.mark.parametrize("precision,tol1,tol50", [("f64", 1e-12, 1e-9), ("f32", 2e-5, 5e-4),
+                                                   ("bf16x3", 5e-5, 1e-3)])
 def test_iterations_match_oracle_c0(ctx, c0, precision, tol1, tol50):
     say("iteration parity c0", precision)
     w = cases.config_weights(0)
@@ -224,18 +225,21 @@ def c1():
     return cases.make_case(1)
 
 
-def test_iteration_parity_c1_f32(ctx, c1):
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_iteration_parity_c1(ctx, c1, precision):
     """Medium case in FP32 (40,000 x 1,440, 81 plans): 3 iterations vs FP64 oracle.
 
     Tolerance: the dose-point iterate q is O(1/rho_min) = O(0.03) while the box
     widths u are O(w/N) = O(5e-4), and q is formed by FP32 products over
     n_t = 1,440 terms; the FP32 rounding of q, eps_32 * sqrt(n_t) / rho_min =
     6e-8 * 38 * 0.03 = 7e-8, is 1.4e-4 of max|z1|.  A CPU emulation of the same
-    FP32 arithmetic shows 1e-4; the bound used is 2e-3 (worst case ~ eps_32 n_t)."""
-    say("iteration parity c1 f32")
+    FP32 arithmetic shows 1e-4; the bound used is 2e-3 (worst case ~ eps_32 n_t).
+    The BF16-pair products (16 significant bits per operand, FP32 accumulation)
+    round at the same order and take the same bound."""
+    say("iteration parity c1", precision)
     w = cases.config_weights(1)
     _, slp, rho = oracle_setup(c1, w)
-    dc = ladmm.Case.from_case(ctx, c1, "f32")
+    dc = ladmm.Case.from_case(ctx, c1, precision)
     b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
     b.iterate(3)
     st = oadmm.admm_iterate(slp, rho, 3)
@@ -246,27 +250,28 @@ def test_iteration_parity_c1_f32(ctx, c1):
         assert err < 2e-3, f"{name} rel err {err:.3e}"
 
 
-def test_solve_c1_f32_sampled_exact(ctx, c1):
-    """FP32 solve of all 81 plans; sampled plans against their exact optimum."""
-    say("solve c1 f32")
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_solve_c1_sampled_exact(ctx, c1, precision):
+    """Solve of all 81 plans; sampled plans against their exact optimum."""
+    say("solve c1", precision)
     path = os.path.join(os.path.dirname(__file__), "golden", "fstar_c1.txt")
     if not os.path.exists(path):
         pytest.skip("fstar_c1.txt not generated")
     fs = golden_fstar(1)
     w = cases.config_weights(1)
-    dc = ladmm.Case.from_case(ctx, c1, "f32")
+    dc = ladmm.Case.from_case(ctx, c1, precision)
     opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
                          tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
     res = ladmm.solve_batch(dc, w, opts=opts)
     rel = {j: abs(res["objective"][j] - f) / f for j, f in fs.items()}
-    say("c1 f32 sampled objective rel err", rel, "iters", res["iters"][list(fs)])
+    say("c1", precision, "sampled objective rel err", rel, "iters", res["iters"][list(fs)])
     # objective recomputed by the oracle from the returned t (FP64)
     F_orc = olp.planning_objective(c1, w, res["t"].T)[0]
     assert rel_err(res["objective"], F_orc) < 1e-5
     assert all(v < 1e-3 for v in rel.values()), rel
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
 def test_tile_configurations_give_identical_results(ctx, c0, precision):
     """Every pair of tile configurations of the two dose-matrix products yields
     the same iterates and the same statistics, bit for bit (the configurations
@@ -289,3 +294,21 @@ def test_tile_configurations_give_identical_results(ctx, c0, precision):
                 continue
             for key, val in res.items():
                 assert np.array_equal(val, ref[key]), (c1, c2, key)
+
+
+def test_solve_bf16x3_matches_exact_optimum_c0(ctx, c0):
+    """The BF16-pair products reach every plan's exact optimum within 1e-3 at
+    the same stopping test as FP64."""
+    say("solve parity c0 bf16x3")
+    w = cases.config_weights(0)
+    dc = ladmm.Case.from_case(ctx, c0, "bf16x3")
+    opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
+                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+    res = ladmm.solve_batch(dc, w, opts=opts)
+    fs = golden_fstar(0)
+    Fstar = np.array([fs[j] for j in range(w.shape[0])])
+    F_orc = olp.planning_objective(c0, w, res["t"].T)[0]
+    assert rel_err(res["objective"], F_orc) < 1e-5
+    rel = np.abs(res["objective"] - Fstar) / Fstar
+    say("c0 bf16x3 objective rel err", rel, "iters", res["iters"])
+    assert np.all(rel < 1e-3), rel

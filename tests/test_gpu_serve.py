@@ -92,10 +92,11 @@ def test_served_plans_equal_plans_solved_alone(ctx, c0, mini):
         assert abs(F[j] - fs) <= 1e-3 * abs(fs) + 1e-9, (j, F[j], fs)
 
 
-def test_slot_reuse_and_masks_match_alone(ctx, mini):
-    """More plans than slots (plans start in freed slots), with LD masks, FP32."""
-    say("serve slot reuse mini f32")
-    dm = ladmm.Case.from_case(ctx, mini, "f32")
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_slot_reuse_and_masks_match_alone(ctx, mini, precision):
+    """More plans than slots (plans start in freed slots), with LD masks."""
+    say("serve slot reuse mini", precision)
+    dm = ladmm.Case.from_case(ctx, mini, precision)
     k = 70
     w = cases.random_weights(k, 6)
     types = mini.point_types()
