@@ -34,12 +34,69 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAKS = {  # MI355X published dense peaks
-    "f32_mfma_tflops": 157.3,
-    "f64_mfma_tflops": 78.6,
-    "hbm_gbs": 8000.0,
+PEAKS = {  # MI355X published dense peaks (TFLOP/s)
+    "f64": 78.6,
+    "f32": 157.3,
+    "bf16x3": 2500.0,    # the BF16 matrix cores
 }
+# MFMA passes per dose-matrix product: the BF16-pair product executes three
+TERMS = {"f64": 1, "f32": 1, "bf16x3": 3}
 ITERS_PER_STEP = 50
+COPY_PROBE_BYTES = 256 << 20
+# HBM traffic per launch of the dose-matrix products, from rocprofv3 counter
+# runs (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); valid
+# only while the kernels' sources are the ones that were measured.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_c1_f32_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_08602_amd", "csrc", f)
+                  for f in ("gemm_impl.h", "gemm_f32.hip", "kernels.h")]
+
+
+def copy_probe():
+    """A plain device-to-device copy of COPY_PROBE_BYTES through the HIP
+    runtime (executed as the runtime's copy kernel), three times: the reference
+    that scales the HBM byte counters."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    for p in (src, dst):
+        if hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(COPY_PROBE_BYTES)) != 0:
+            raise RuntimeError("hipMalloc failed")
+    try:
+        if hip.hipMemset(src, 1, ctypes.c_size_t(COPY_PROBE_BYTES)) != 0:
+            raise RuntimeError("hipMemset failed")
+        for _ in range(3):
+            for a, b in ((dst, src), (src, dst)):
+                if hip.hipMemcpy(a, b, ctypes.c_size_t(COPY_PROBE_BYTES), 3) != 0:   # device to device
+                    raise RuntimeError("hipMemcpy failed")
+        hip.hipDeviceSynchronize()
+    finally:
+        hip.hipFree(src)
+        hip.hipFree(dst)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, config_name):
+    """Bytes per launch recorded for `kernel` on this workload, or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line.startswith("#") or "=" not in line:
+            continue
+        key, val = line.split("=", 1)
+        rec[key.strip()] = val.strip()
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("workload") != config_name:
+        return None
+    v = rec.get(f"{kernel}_bytes_per_launch")
+    return float(v) if v else None
 
 
 def parse():
@@ -52,6 +109,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="step", choices=("step", "uneven", "serve"),
+                    help="step: iterations of one configuration (default); uneven: 32 cases "
+                         "of uneven size served together; serve: Poisson request arrivals")
+    ap.add_argument("--cases", type=int, default=None)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--requests", type=int, default=64)
     return ap.parse_args()
 
 
@@ -79,16 +143,144 @@ def cpu_baseline(case, w, rho0, budget_s):
                        f"same case ({dt:.1f} s; setup excluded)")
 
 
+def uneven(args):
+    """32 seeded cases between the small and the large configuration, 81 plans
+    each, FP32, all resident and served together (one lane per case, each on
+    its own stream): aggregate plan-iterations/s over a fixed iteration budget."""
+    from synth import cases
+    from paper_2509_08602_amd import ladmm
+    n_cases = args.cases or 32
+    iters = ITERS_PER_STEP * max(1, args.steps // 4)
+    ctx = ladmm.Context(0)
+    dcs, sizes, setup = [], [], 0.0
+    for s in range(1000, 1000 + n_cases):
+        c = cases.uneven_case(s)
+        dc = ladmm.Case.from_case(ctx, c, "f32")
+        setup += dc.setup_ms
+        dcs.append(dc)
+        sizes.append((c.n_points, c.n_t))
+        del c
+    w = cases.config_weights(1)
+    srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
+    fixed = lambda n: ladmm.Options(max_iter=n, check_every=ITERS_PER_STEP, tol_gap=0.0,
+                                    rho0=1000.0, w0_bot=cases.W0_BOT)
+    for t in [srv.submit(dc, w, opts=fixed(ITERS_PER_STEP)) for dc in dcs]:   # lanes + tiles
+        t.wait()
+    t0 = time.perf_counter()
+    ts = [srv.submit(dc, w, opts=fixed(iters)) for dc in dcs]
+    for t in ts:
+        t.wait()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    k = w.shape[0]
+    value = n_cases * k * iters / wall
+    flops = sum(4.0 * N * nt * k for N, nt in sizes) * iters
+    print(json.dumps({
+        "metric": "plan-iterations/s", "value": round(value, 1), "unit": "plan-iterations/s",
+        "n_gpus": 1, "steps": iters // ITERS_PER_STEP, "warmup": 1,
+        "ms_per_step": round(wall * 1000 * ITERS_PER_STEP / iters, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n_cases} uneven cases (N {min(s[0] for s in sizes)}-"
+                               f"{max(s[0] for s in sizes)}, n_t {min(s[1] for s in sizes)}-"
+                               f"{max(s[1] for s in sizes)}), {k} plans each, f32, served "
+                               f"together", "cases": n_cases, "plans_per_case": k,
+                   "iterations": iters, "setup_ms_total": round(setup, 1)},
+        "dose_product_tflops": round(flops / wall / 1e12, 2),
+        "lanes": st["lanes"], "hbm_gb": round(ctx.used_bytes / 1e9, 2)}))
+
+
+def serve(args):
+    """Serving: resident cases of uneven size, Poisson arrivals of requests of
+    1, 9, 81 or 441 plans (probabilities 0.5 / 0.3 / 0.15 / 0.05) on a random
+    case, solved to a 1e-3 gap.  Capacity is measured closed-loop first; then
+    arrivals at 0.5, 0.8 and 0.95 of it; p50 / p99 latency per level."""
+    from synth import cases
+    from paper_2509_08602_amd import ladmm
+    n_cases = args.cases or 16
+    ctx = ladmm.Context(0)
+    dcs = []
+    for s in range(1000, 1000 + n_cases):
+        c = cases.uneven_case(s)
+        dcs.append(ladmm.Case.from_case(ctx, c, "f32"))
+        del c
+    rng = np.random.default_rng(2000)
+    grids = {9: cases.config_weights(0), 81: cases.config_weights(1),
+             441: cases.config_weights(2)}
+
+    def draw():
+        size = int(rng.choice([1, 9, 81, 441], p=[0.5, 0.3, 0.15, 0.05]))
+        w = (cases.slider_weights(rng.uniform(size=1), rng.uniform(size=1)) if size == 1
+             else grids[size])
+        return int(rng.integers(n_cases)), w
+
+    opts = ladmm.Options(max_iter=3000, check_every=ITERS_PER_STEP, tol_gap=1e-3, tol_pri=1e-3,
+                         tol_dual=1e-3, rho0=1000.0, w0_bot=cases.W0_BOT)
+    # warm-up: one lane per case (tile choice included)
+    srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
+    for t in [srv.submit(dc, grids[9][:1], opts=opts) for dc in dcs]:
+        t.wait()
+    srv.close()
+
+    reqs = [draw() for _ in range(args.requests)]   # the same sequence at every level
+
+    def run(load_rps, n):
+        arr = np.random.default_rng(2001)
+        gaps = arr.exponential(1.0 / load_rps, size=n) if load_rps else np.zeros(n)
+        s = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
+        t0 = time.perf_counter()
+        due, ts = t0, []
+        for (ci, w), g in zip(reqs, gaps):
+            due += g
+            delay = due - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ts.append(s.submit(dcs[ci], w, opts=opts))
+        for t in ts:
+            t.wait()
+        wall = time.perf_counter() - t0
+        st = s.stats()
+        s.close()
+        plans = sum(w.shape[0] for _, w in reqs)
+        return dict(requests=n, plans=plans, seconds=round(wall, 3), p50_ms=round(st["p50_ms"], 2),
+                    p99_ms=round(st["p99_ms"], 2), max_ms=round(st["max_ms"], 2),
+                    plan_iterations_per_s=round(st["plan_iterations"] / wall, 1),
+                    completed=st["completed"])
+
+    cal = run(0.0, args.requests)
+    capacity = cal["requests"] / cal["seconds"]
+    levels = []
+    for load in (0.5, 0.8, 0.95):
+        r = run(load * capacity, args.requests)
+        r.update(load=load, offered_rps=round(load * capacity, 4))
+        levels.append(r)
+    mid = levels[1]
+    print(json.dumps({
+        "metric": "p99 latency at 0.8 of capacity", "value": mid["p99_ms"], "unit": "ms",
+        "n_gpus": 1, "steps": args.requests, "warmup": 1, "ms_per_step": mid["p50_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {n_cases} resident uneven cases, Poisson arrivals of "
+                               "1/9/81/441-plan requests (p 0.5/0.3/0.15/0.05), 1e-3 gap, "
+                               "cold start", "cases": n_cases, "requests_per_level": args.requests},
+        "capacity_rps": round(capacity, 4), "closed_loop": cal, "levels": levels,
+        "hbm_gb": round(ctx.used_bytes / 1e9, 2)}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.workload == "uneven":
+        return uneven(args)
+    if args.workload == "serve":
+        return serve(args)
     from synth import cases
     from paper_2509_08602_amd import ladmm
 
     cfg = args.config
-    precision = args.precision or {0: "f64", 1: "f32", 2: "f32"}[cfg]
+    precision = args.precision or {0: "f64", 1: "f32", 2: "bf16x3"}[cfg]
     case = cases.make_case(cfg)
     w = cases.config_weights(cfg)
     k = w.shape[0]
@@ -114,18 +306,20 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     value = k * ITERS_PER_STEP * args.steps / wall
 
-    # roofline of the dominant kernel (by accumulated device time)
+    # roofline of the dominant kernel (by accumulated device time): the
+    # product's flops for the k plans (2 N n_t k per MFMA pass) per launch
     N, n_t = case.n_points, case.n_t
-    flops_gemm = 2.0 * N * n_t * k
+    flops_gemm = 2.0 * N * n_t * k * TERMS[precision]
     dom = max(("gemm1", "gemm2"), key=lambda c: ktimes[c][0])
     tot, cnt = ktimes[dom]
     avg_ms = tot / max(cnt, 1)
     achieved = flops_gemm / (avg_ms * 1e-3) / 1e12
-    peak = PEAKS["f32_mfma_tflops"] if precision == "f32" else PEAKS["f64_mfma_tflops"]
+    peak = PEAKS[precision]
+    traffic = measured_traffic(dom, case.name) if precision == "f32" else None
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=None, kernel=dom,
+                    frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
                     avg_launch_ms=round(avg_ms, 5),
-                    algorithmic_flops_per_launch=flops_gemm)
+                    algorithmic_flops_per_launch=flops_gemm, mfma_passes=TERMS[precision])
     kernels = {c: dict(total_ms=round(v[0], 3), launches=v[1],
                        avg_ms=round(v[0] / v[1], 5) if v[1] else None)
                for c, v in ktimes.items()}
@@ -140,6 +334,9 @@ def main():
                      converged=int(np.sum(out["plan_status"] == ladmm.PLAN_CONVERGED)),
                      max_iters=int(out["iters"].max()), median_iters=float(np.median(out["iters"])),
                      max_rel_gap=float(out["rel_gap"].max()))
+
+    if args.copy_probe:
+        copy_probe()
 
     cpu = None
     if not args.no_cpu_baseline:

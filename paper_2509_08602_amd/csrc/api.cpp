@@ -824,7 +824,7 @@ void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np 
 bool cfg_ok(const ladmm_batch *b, int which, int cfg) {
   const ladmm_case *c = b->c;
   if (c->precision == LADMM_BF16X3)
-    return which == 0 ? gemm_bf_cfg_ok(cfg, c->ntp, b->kp) : gemm_bf_cfg_ok(cfg, c->Np, b->kp);
+    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kp) : gemm_bf_cfg_ok(1, cfg, c->Np, b->kp);
   return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kp) : gemm_nn_cfg_ok(cfg, c->Np, b->kp);
 }
 

@@ -40,6 +40,16 @@ __device__ __forceinline__ void split_pair(double x, uint16_t &h, uint16_t &l) {
 
 __device__ __forceinline__ float clip0u_f(float q, float u) { return fminf(fmaxf(q, 0.f), u); }
 
+// Consecutive tile indices on one XCD (workgroups go round-robin over the 8
+// XCDs); a bijection on [0, total).
+__device__ __forceinline__ int xcd_tile_bf(int id, int total) {
+  constexpr int X = 8;
+  const int per = (total + X - 1) / X;
+  const int tall = total % X == 0 ? X : total % X;
+  const int xcd = id % X, local = id / X;
+  return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+}
+
 __device__ __forceinline__ float upper_bf(const PointTable<float> &pt, int g, int p, int j) {
   float u = pt.utab[(size_t)g * pt.ldu + j];
   if (pt.mask != nullptr && pt.is_ld[g]) {
@@ -53,8 +63,11 @@ constexpr int kBfBK = 32;              // one MFMA k-step per stage
 constexpr int kBfLd = kBfBK + 8;       // LDS row: 80 bytes, 8 rows cover all banks
 
 // MODE 0: split-K partial store; otherwise the NN epilogue EPI_ADMM / _STATS / _OBJ.
-template <int BM, int BN, int WM, int WN, int TERMS, int MODE>
+// NBUF: 2 = double-buffered LDS stages; 1 = one stage (half the LDS, so more
+// workgroups per CU), the next stage waiting in registers behind a barrier.
+template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, int K, int kchunk,
+                                                         int mtiles, int ntiles,
                                                          float *__restrict__ P, int ldp,
                                                          size_t pstride, EpiArgs<float> ea) {
   constexpr int NT = 64 * WM * WN;
@@ -68,8 +81,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
   constexpr int NST = (MODE == EPI_OBJ) ? kObjStats : kAdmmStats;
   constexpr bool kStats = MODE == EPI_ADMM_STATS || MODE == EPI_OBJ;
   constexpr int T16 = BM / 16;
-  constexpr size_t kTileA = sizeof(uint16_t) * 2 * BM * kBfLd;
-  constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
+  constexpr size_t kTileA = sizeof(uint16_t) * NBUF * BM * kBfLd;
+  constexpr size_t kTileB = sizeof(uint16_t) * NBUF * BN * kBfLd;
   constexpr size_t kBytesT = kTileA * (ALO ? 2 : 1) + kTileB * 2;
   constexpr size_t kBytesR = kStats ? sizeof(double) * T16 * NST * BN : 0;
   constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
@@ -82,8 +95,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int kbeg = MODE == 0 ? blockIdx.z * kchunk : 0;
+  // tile order: column blocks fastest (they share the row slab of A), then
+  // row tiles (which share a split-K chunk of B), then chunks
+  const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
+  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = MODE == 0 ? zc * kchunk : 0;
   const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
 
   f4v acc[TM][TN];
@@ -166,14 +183,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
           acc[tm][tn] = mfma_bf(ah[tm], bl[tn], acc[tm][tn]);
           if (ALO) acc[tm][tn] = mfma_bf(al[tm], bh[tn], acc[tm][tn]);
         }
-      if (more) store(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+      if (NBUF == 2) {
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      } else {
+        __syncthreads();          // every wave has read the stage
+        if (more) store(0);
+        __syncthreads();
+      }
     }
   }
 
   if (MODE == 0) {
-    float *Pz = P + (size_t)blockIdx.z * pstride;
+    float *Pz = P + (size_t)zc * pstride;
 #pragma unroll
     for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -267,32 +290,49 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
     const int b = e / (NST * BN), q = (e / BN) % NST, c = e % BN;
     const double t0 = sred[2 * b][q][c], t1 = sred[2 * b + 1][q][c];
     const double v = (MODE == EPI_OBJ && q == 1) ? fmax(t0, t1) : t0 + t1;
-    ea.stats[((size_t)(blockIdx.x * (BM / 32) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
+    ea.stats[((size_t)(mt * (BM / 32) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
   }
 }
 
-// Tile configurations (rows BM, columns BN, wavefront grid WM x WN).
-struct BfCfg { int bm, bn, wm, wn; };
-static const BfCfg kBfCfgs[kGemmCfgs] = {{64, 32, 2, 1}, {128, 32, 2, 1}, {128, 64, 2, 1}, {64, 64, 1, 1}};
+// Tile configurations (rows BM, columns BN, wavefront grid WM x WN, LDS
+// stages) of the split-K product (which = 0) and the point-row product (1).
+struct BfCfg { int bm, bn, wm, wn, nbuf; };
+static const BfCfg kBfCfgs[2][kGemmCfgs] = {
+    {{64, 32, 2, 1, 2}, {64, 64, 2, 1, 1}, {64, 64, 4, 1, 1}, {128, 64, 4, 1, 1}},
+    {{64, 32, 2, 1, 2}, {128, 32, 4, 1, 1}, {128, 64, 4, 1, 1}, {256, 64, 4, 1, 1}}};
 
-bool gemm_bf_cfg_ok(int cfg, int M, int N) {
+bool gemm_bf_cfg_ok(int which, int cfg, int M, int N) {
   if (cfg < 0 || cfg >= kGemmCfgs) return false;
-  const BfCfg c = kBfCfgs[cfg];
+  const BfCfg c = kBfCfgs[which][cfg];
   return M % c.bm == 0 && N % c.bn == 0;
 }
 
 template <int MODE, int TERMS>
-static hipError_t launch_bf(int cfg, dim3 grid, hipStream_t s, BfPair A, BfPair B, int K, int kchunk,
-                            float *P, int ldp, size_t pstride, const EpiArgs<float> &ea) {
-#define BF_ONE(BMv, BNv, WMv, WNv)                                                               \
-  hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE>), grid, dim3(64 * WMv * WNv), 0, s, \
-                     A, B, K, kchunk, P, ldp, pstride, ea)
-  switch (cfg) {
-    case 0: BF_ONE(64, 32, 2, 1); break;
-    case 1: BF_ONE(128, 32, 2, 1); break;
-    case 2: BF_ONE(128, 64, 2, 1); break;
-    case 3: BF_ONE(64, 64, 1, 1); break;
-    default: return hipErrorInvalidValue;
+static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, BfPair A, BfPair B,
+                            int K, int kchunk, float *P, int ldp, size_t pstride,
+                            const EpiArgs<float> &ea) {
+  const BfCfg c = kBfCfgs[MODE == 0 ? 0 : 1][cfg];
+  const int mtiles = M / c.bm, ntiles = N / c.bn;
+  const dim3 grid(mtiles * ntiles * nchunk);
+#define BF_ONE(BMv, BNv, WMv, WNv, NB)                                                             \
+  hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE, NB>), grid, dim3(64 * WMv * WNv), 0, \
+                     s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
+  if (MODE == 0) {
+    switch (cfg) {
+      case 0: BF_ONE(64, 32, 2, 1, 2); break;
+      case 1: BF_ONE(64, 64, 2, 1, 1); break;
+      case 2: BF_ONE(64, 64, 4, 1, 1); break;
+      case 3: BF_ONE(128, 64, 4, 1, 1); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (cfg) {
+      case 0: BF_ONE(64, 32, 2, 1, 2); break;
+      case 1: BF_ONE(128, 32, 4, 1, 1); break;
+      case 2: BF_ONE(128, 64, 4, 1, 1); break;
+      case 3: BF_ONE(256, 64, 4, 1, 1); break;
+      default: return hipErrorInvalidValue;
+    }
   }
 #undef BF_ONE
   return hipGetLastError();
@@ -300,28 +340,24 @@ static hipError_t launch_bf(int cfg, dim3 grid, hipStream_t s, BfPair A, BfPair 
 
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg) {
-  if (!gemm_bf_cfg_ok(cfg, M, N)) cfg = 0;
-  if (!gemm_bf_cfg_ok(cfg, M, N) || nchunk < 1 || K % 8 || A.ld % 8 || B.ld % 8)
+  if (!gemm_bf_cfg_ok(0, cfg, M, N)) cfg = 0;
+  if (!gemm_bf_cfg_ok(0, cfg, M, N) || nchunk < 1 || K % 8 || A.ld % 8 || B.ld % 8)
     return hipErrorInvalidValue;
   int kchunk = (K + nchunk - 1) / nchunk;
   kchunk = (kchunk + 31) / 32 * 32;
-  const BfCfg c = kBfCfgs[cfg];
-  const dim3 grid(M / c.bm, N / c.bn, nchunk);
   const EpiArgs<float> ea{};
   const size_t pstride = (size_t)M * ldp;
-  return terms == 3 ? launch_bf<0, 3>(cfg, grid, s, A, B, K, kchunk, P, ldp, pstride, ea)
-                    : launch_bf<0, 2>(cfg, grid, s, A, B, K, kchunk, P, ldp, pstride, ea);
+  return terms == 3 ? launch_bf<0, 3>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea)
+                    : launch_bf<0, 2>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea);
 }
 
 hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
                       const EpiArgs<float> &ea, int terms, int cfg) {
-  if (!gemm_bf_cfg_ok(cfg, M, N)) cfg = 0;
-  if (!gemm_bf_cfg_ok(cfg, M, N) || K % kBfBK || A.ld % 8 || B.ld % 8) return hipErrorInvalidValue;
-  const BfCfg c = kBfCfgs[cfg];
-  const dim3 grid(M / c.bm, N / c.bn, 1);
+  if (!gemm_bf_cfg_ok(1, cfg, M, N)) cfg = 0;
+  if (!gemm_bf_cfg_ok(1, cfg, M, N) || K % kBfBK || A.ld % 8 || B.ld % 8) return hipErrorInvalidValue;
 #define BF_EPI(E)                                                                               \
-  return terms == 3 ? launch_bf<E, 3>(cfg, grid, s, A, B, K, K, nullptr, 0, 0, ea)              \
-                    : launch_bf<E, 2>(cfg, grid, s, A, B, K, K, nullptr, 0, 0, ea)
+  return terms == 3 ? launch_bf<E, 3>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)           \
+                    : launch_bf<E, 2>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)
   switch (epi) {
     case EPI_ADMM: BF_EPI(EPI_ADMM);
     case EPI_ADMM_STATS: BF_EPI(EPI_ADMM_STATS);

@@ -75,6 +75,18 @@ __device__ __forceinline__ T upper_of(const PointTable<T> &pt, int g, int p, int
 template <typename T>
 __device__ __forceinline__ T clip0u(T q, T u) { return fmin(fmax(q, T(0)), u); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumber them so that consecutive tile indices run on the same XCD: tiles
+// that share an operand slab (the column blocks of a row slab, the row tiles
+// of a split-K chunk) then share one L2.  A bijection on [0, total).
+__device__ __forceinline__ int xcd_tile(int id, int total) {
+  constexpr int X = 8;
+  const int per = (total + X - 1) / X;
+  const int tall = total % X == 0 ? X : total % X;   // XCDs that take `per` tiles
+  const int xcd = id % X, local = id / X;
+  return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+}
+
 // Padding (in elements) that makes a row of W + pad elements of T span 16 (mod
 // 32) LDS banks, so two half-wavefronts reading consecutive rows never collide.
 template <typename T, int W>
@@ -90,7 +102,8 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, bool PRO>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(const T *__restrict__ A, int lda,
                                                           const T *__restrict__ B, int ldb,
                                                           T *__restrict__ P, int ldp, size_t pstride,
-                                                          int K, int kchunk, PointTable<T> pt) {
+                                                          int K, int kchunk, int mtiles, int ntiles,
+                                                          PointTable<T> pt) {
   constexpr int NT = 64 * WM * WN;
   constexpr int VN = V16<T>::n;
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
@@ -103,8 +116,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(const T *__restrict__ 
   __shared__ T sB[2][BK][BN + PADB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int kbeg = blockIdx.z * kchunk;
+  // tile order: column blocks fastest (they share the row slab of A), then
+  // row tiles (which share a split-K chunk of B), then chunks
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = zc * kchunk;
   const int kend = min(K, kbeg + kchunk);
   typename MV<T>::V acc[TM][TN];
 #pragma unroll
@@ -190,7 +207,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_tn(const T *__restrict__ 
       buf ^= 1;
     }
   }
-  T *Pz = P + (size_t)blockIdx.z * pstride;
+  T *Pz = P + (size_t)zc * pstride;
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -232,15 +249,16 @@ hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P
   if (pro) pt = *pro;
   const int BN = pick_bn(N);
   const TnCfg c = kTnCfgs[cfg];
-  dim3 grid(M / c.bm, N / BN, nchunk);
+  const int mtiles = M / c.bm, ntiles = N / BN;
+  const dim3 grid(mtiles * ntiles * nchunk);
 #define TN_ONE(BMv, BNv, BKv, WMv, WNv)                                                       \
   do {                                                                                       \
     if (pro)                                                                                 \
       hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BKv, WMv, WNv, true>), grid, dim3(64 * WMv * WNv), \
-                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
+                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, mtiles, ntiles, pt); \
     else                                                                                     \
       hipLaunchKernelGGL((k_gemm_tn<T, BMv, BNv, BKv, WMv, WNv, false>), grid, dim3(64 * WMv * WNv), \
-                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, pt);                \
+                         0, s, A, lda, B, ldb, P, ldp, pstride, K, kchunk, mtiles, ntiles, pt); \
   } while (0)
 #define TN_BN(BMv, BKv, WMv, WNv)                                  \
   switch (BN) {                                               \
@@ -267,7 +285,7 @@ hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P
 template <typename T, int BM, int BN, int BK, int WM, int WN, int EPI>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ A, int lda,
                                                           const T *__restrict__ B, int ldb, int K,
-                                                          EpiArgs<T> ea) {
+                                                          int ntiles, EpiArgs<T> ea) {
   constexpr int NT = 64 * WM * WN;
   constexpr int VN = V16<T>::n;
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
@@ -292,7 +310,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
   auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);   // [16-row tile][stat][column]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  // tile order: the column blocks of a row slab are consecutive
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int mt = tile / ntiles, nt = tile % ntiles;
+  const int m0 = mt * BM, n0 = nt * BN;
   typename MV<T>::V acc[TM][TN];
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -464,7 +485,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
     const int b = e / (NST * BN), q = (e / BN) % NST, c = e % BN;
     const double t0 = sred[2 * b][q][c], t1 = sred[2 * b + 1][q][c];
     const double v = (EPI == EPI_OBJ && q == 1) ? fmax(t0, t1) : t0 + t1;
-    ea.stats[((size_t)(blockIdx.x * (BM / 32) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
+    ea.stats[((size_t)(mt * (BM / 32) + b) * NST + q) * ea.nstat_cols + n0 + c] = v;
   }
 }
 
@@ -488,10 +509,11 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
   if (lda % V16<T>::n || ldb % V16<T>::n) return hipErrorInvalidValue;
   const NnCfg c = kNnCfgs[cfg];
   const int BN = nn_bn(c, N);
-  const dim3 grid(M / c.bm, N / BN);
+  const int ntiles = N / BN;
+  const dim3 grid((M / c.bm) * ntiles);
 #define NN_ONE(BMv, BNv, WMv, WNv, E)                                                          \
   hipLaunchKernelGGL((k_gemm_nn<T, BMv, BNv, BK, WMv, WNv, E>), grid, dim3(64 * WMv * WNv), 0, s, \
-                     A, lda, B, ldb, K, ea)
+                     A, lda, B, ldb, K, ntiles, ea)
 #define NN_E(BMv, BNv, WMv, WNv)                                          \
   switch (epi) {                                                         \
     case EPI_STORE: NN_ONE(BMv, BNv, WMv, WNv, EPI_STORE); break;        \

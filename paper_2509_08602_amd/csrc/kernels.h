@@ -6,7 +6,7 @@
 namespace ladmm {
 
 // Tile sizes shared by the launchers and the host-side padding rules.
-constexpr int kTileRows = 128;    // dose-point rows of a GEMM2 tile (point padding)
+constexpr int kTileRows = 256;    // dose-point padding: a multiple of every row tile
 constexpr int kSmallAlign = 64;   // padding of the shot / small-row dimension
 
 // Layout of the small (m_A) vectors: shot rows t in [0, ntp) (t < n_t real),
@@ -164,7 +164,7 @@ hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const doubl
 // A_hi B_hi + A_hi B_lo (+ A_lo B_hi with terms = 3) on the BF16 MFMA with FP32
 // accumulation, in the same order for every tile configuration.
 struct BfPair { const uint16_t *hi, *lo; int ld; };
-bool gemm_bf_cfg_ok(int cfg, int M, int N);
+bool gemm_bf_cfg_ok(int which, int cfg, int M, int N);   // which: 0 split-K, 1 point-row
 // P[z][m][n] = sum over rows k of chunk z of A[m][k] B[n][k]  (split-K partials, FP32)
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg);

@@ -397,6 +397,43 @@ def config_spec(config: int) -> dict:
     raise ValueError(f"unknown config {config}")
 
 
+def uneven_spec(seed: int) -> dict:
+    """A case of the uneven multi-case workload: one u ~ U[0, 1] per seed sets
+    the size between the small and the large configuration on a log scale,
+    N = 2,400 (200,000 / 2,400)^u points and n_iso = round(8 * 25^u)
+    isocentres (real N and n_iso grow together); 1 + round(8 u) targets share
+    a target volume of 900 (52,000 / 900)^u voxels; a tenth of the points are
+    low-dose points, the rest ring points."""
+    rng = np.random.default_rng(seed)
+    u = float(rng.uniform())
+    n_total = int(round(2400 * (200000 / 2400) ** u))
+    n_iso = max(1, int(round(8 * 25 ** u)))
+    n_tg = 1 + int(round(8 * u))
+    vol = 900.0 * (52000.0 / 900.0) ** u
+    share = rng.uniform(0.5, 1.5, size=n_tg)
+    share /= share.sum()
+    radii = [tuple(float(x) for x in (3.0 * vol * s / (4.0 * np.pi)) ** (1.0 / 3.0)
+                   * rng.uniform(0.9, 1.1, size=3)) for s in share]
+    side = int(48 + 120 * u)
+    for _ in range(20):
+        try:
+            centers = _spread_targets(radii, (side, side, side), rng, gap=4.0)
+            break
+        except RuntimeError:
+            side += 16
+    tg = [(tuple(c), r, 20.0) for c, r in zip(centers, radii)]
+    n_target = sum(int(_ellipsoid_mask((side,) * 3, c, r).sum()) for c, r, _ in tg)
+    n_ld = max(500, n_total // 10)
+    return dict(name=f"uneven-{seed}-u{u:.3f}", grid=(side,) * 3, targets=tg,
+                n_ring=max(200, n_total - n_target - n_ld), ring_mm=3.0, n_ld=n_ld,
+                ld_region=("shell", 10.0 + 5.0 * u), n_iso=n_iso)
+
+
+def uneven_case(seed: int, dtype=np.float64) -> Case:
+    """The seeded case of the uneven multi-case and serving workloads."""
+    return build_case(uneven_spec(seed), seed, dtype=dtype)
+
+
 CONFIG_SEEDS = {0: 0, 1: 1, 2: 2}
 CONFIG_PLANS = {0: 3, 1: 9, 2: 21}   # slider grid edge g; plans k = g * g
 
