@@ -42,6 +42,7 @@ PEAKS = {  # MI355X published dense peaks (TFLOP/s)
 # MFMA passes per dose-matrix product: the BF16-pair product executes three
 TERMS = {"f64": 1, "f32": 1, "bf16x3": 3}
 ITERS_PER_STEP = 50
+RHO0 = 1e4      # step-size rule constant (Eq. rho_rule), from a grid over 30..1e4
 COPY_PROBE_BYTES = 256 << 20
 # HBM traffic per launch of the dose-matrix products, from rocprofv3 counter
 # runs (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); valid
@@ -72,6 +73,32 @@ def copy_probe():
     finally:
         hip.hipFree(src)
         hip.hipFree(dst)
+
+
+def two_pass_sweep(ctx, case, w, precision, opts, max_vox=60000):
+    """Both passes of Sec. 2.C for every plan: pass 1, the low-dose band of the
+    pass-1 dose on candidate voxels (D_LD = D_T / 2, width D_T / 10), Algorithm 1
+    (N_LD = 5,000 per plan, capped at the candidate count / 4) and pass 2 on the
+    rebuilt case.  Candidates: an even subsample of the case's low-dose region."""
+    from paper_2509_08602_amd import ladmm
+    from synth import cases
+    cand = case.ld_candidates
+    if len(cand) == 0:
+        return None
+    cand = cand[np.linspace(0, len(cand) - 1, min(len(cand), max_vox)).astype(np.int64)]
+    phi = case.kernel.dose_rate(cand)
+    ld_group = [g.type for g in case.groups].index(cases.LD)
+    n_ld = min(5000, len(cand) // 4)
+    t0 = time.perf_counter()
+    r1, r2, P, n2, tms = ladmm.two_pass(ctx, case, w, phi, 0.5 * case.prescription_mean,
+                                        0.1 * case.prescription_mean, n_ld, 7, ld_group,
+                                        precision=precision, opts=opts)
+    wall = time.perf_counter() - t0
+    return dict(seconds=round(wall, 4), candidates=int(len(cand)), selected_points=int(len(P)),
+                pass2_points=int(n2), times_ms=dict(zip(("setup1", "pass1", "band_alg1", "setup2",
+                                                         "pass2"), [round(x, 2) for x in tms])),
+                pass2_converged=int(np.sum(r2["plan_status"] == ladmm.PLAN_CONVERGED)),
+                pass2_max_iters=int(r2["iters"].max()))
 
 
 def kernel_source_hash():
@@ -163,7 +190,7 @@ def uneven(args):
     w = cases.config_weights(1)
     srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
     fixed = lambda n: ladmm.Options(max_iter=n, check_every=ITERS_PER_STEP, tol_gap=0.0,
-                                    rho0=1000.0, w0_bot=cases.W0_BOT)
+                                    rho0=RHO0, w0_bot=cases.W0_BOT)
     for t in [srv.submit(dc, w, opts=fixed(ITERS_PER_STEP)) for dc in dcs]:   # lanes + tiles
         t.wait()
     t0 = time.perf_counter()
@@ -215,7 +242,7 @@ def serve(args):
         return int(rng.integers(n_cases)), w
 
     opts = ladmm.Options(max_iter=3000, check_every=ITERS_PER_STEP, tol_gap=1e-3, tol_pri=1e-3,
-                         tol_dual=1e-3, rho0=1000.0, w0_bot=cases.W0_BOT)
+                         tol_dual=1e-3, rho0=RHO0, w0_bot=cases.W0_BOT, adapt_rho=True)
     # warm-up: one lane per case (tile choice included)
     srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
     for t in [srv.submit(dc, grids[9][:1], opts=opts) for dc in dcs]:
@@ -284,7 +311,7 @@ def main():
     case = cases.make_case(cfg)
     w = cases.config_weights(cfg)
     k = w.shape[0]
-    rho0 = 1000.0
+    rho0 = RHO0
     ctx = ladmm.Context(0)
     dc = ladmm.Case.from_case(ctx, case, precision)
     setup_ms = dc.setup_ms
@@ -333,7 +360,10 @@ def main():
         sweep = dict(plans=k, seconds=round(time.perf_counter() - t1, 4), tol_gap=1e-3,
                      converged=int(np.sum(out["plan_status"] == ladmm.PLAN_CONVERGED)),
                      max_iters=int(out["iters"].max()), median_iters=float(np.median(out["iters"])),
-                     max_rel_gap=float(out["rel_gap"].max()))
+                     max_rel_gap=float(out["rel_gap"].max()), passes=1)
+        two = two_pass_sweep(ctx, case, w, precision, opts)
+        if two:
+            sweep["two_pass"] = two
 
     if args.copy_probe:
         copy_probe()

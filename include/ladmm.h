@@ -116,6 +116,16 @@ typedef struct {
   double rho0, w0_bot;
   int32_t autotune;   /* nonzero: time the tile configurations before the first
                          iteration (see ladmm_batch_tiles); 0: configuration 0 */
+  /* Per-plan step-size balancing (extension of the fixed rule of Sec. 3.C):
+   * with adapt_rho nonzero, at every check of ladmm_batch_run / solve / serve
+   * a running plan's rho is multiplied by adapt_tau when r_pri > adapt_mu *
+   * r_dual and divided by it when r_dual > adapt_mu * r_pri, within a factor
+   * 1e3 of its starting value; its scaled duals are rescaled so that the
+   * multipliers rho * y (and the shot times) do not change.  S does not depend
+   * on rho, so nothing is refactored.  adapt_tau = 2 keeps every rescale
+   * exact.  adapt_mu > 1, adapt_tau > 1. */
+  int32_t adapt_rho;
+  double adapt_mu, adapt_tau;
 } ladmm_opts;
 
 /* Per-plan results; every pointer is caller-owned host memory or NULL.

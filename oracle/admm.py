@@ -118,3 +118,43 @@ def residuals(slp: ScaledLP, rho, state: ADMMState):
     r_dual = (rho * np.linalg.norm(z - zp, axis=0)
               / np.maximum(rho * np.linalg.norm(y, axis=0), 1e-300))
     return r_pri, r_dual
+
+
+def admm_adaptive(slp: ScaledLP, rho, iters: int, check_every: int, mu: float = 10.0,
+                  tau: float = 2.0, rho_range: float = 1e3, state: ADMMState | None = None,
+                  factor=None):
+    """Eq. (admm) with per-plan step sizes balanced at every check.
+
+    The step sizes start from the rule of Sec. 3.C (rho) and, after every
+    `check_every` iterations, each plan's rho is multiplied by tau when its
+    relative primal residual exceeds mu times its relative dual residual, and
+    divided by tau in the opposite case (residual balancing), within
+    [rho / rho_range, rho * rho_range] of its starting value.  The scaled duals
+    are multiplied by rho_old / rho_new so that the multipliers rho * y, and
+    hence the iterate, are unchanged by the switch.  S does not depend on rho,
+    so no refactorisation is needed.  Returns (state, final rho).
+    """
+    rho_start = np.asarray(rho, np.float64).ravel()
+    rho = rho_start.copy()
+    st = zero_state(slp, rho.size) if state is None else state.copy()
+    if factor is None:
+        factor, _ = schur_factor(slp)
+    done = 0
+    while done < iters:
+        n = min(check_every, iters - done)
+        st = admm_iterate(slp, rho, n, st, factor)
+        done += n
+        if n < check_every:
+            break
+        r_pri, r_dual = residuals(slp, rho, st)
+        new = rho.copy()
+        up = r_pri > mu * r_dual
+        down = r_dual > mu * r_pri
+        new[up] *= tau
+        new[down] /= tau
+        new = np.clip(new, rho_start / rho_range, rho_start * rho_range)
+        scale = rho / new
+        st.y1 = st.y1 * scale[None, :]
+        st.y2 = st.y2 * scale[None, :]
+        rho = new
+    return st, rho

@@ -464,6 +464,7 @@ int destroy_batch_impl(ladmm_batch *b) {
   for (void *p : b->allocs) hipFree(p);
   ctx_release(b->c->ctx, b->bytes);
   if (b->h_fin) hipHostFree(b->h_fin);
+  if (b->h_fac) hipHostFree(b->h_fac);
   if (b->ev0) hipEventDestroy(b->ev0);
   if (b->ev1) hipEventDestroy(b->ev1);
   if (b->stream) hipStreamDestroy(b->stream);
@@ -564,6 +565,9 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   }
   if (!slots && !rho && (!(opts->rho0 > 0) || !(opts->w0_bot > 0)))
     return fail(LADMM_E_INVALID, "rho0 and w0_bot must be > 0");
+  if (opts->adapt_rho && (!(opts->adapt_mu > 1) || !(opts->adapt_tau > 1) ||
+                          !std::isfinite(opts->adapt_mu) || !std::isfinite(opts->adapt_tau)))
+    return fail(LADMM_E_INVALID, "adapt_mu and adapt_tau must be finite and > 1");
 
   {
     int rc = case_ref(c);
@@ -587,7 +591,8 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   b->status.assign(k, slots ? LADMM_PLAN_CONVERGED : LADMM_PLAN_RUNNING);
   b->iters.assign(k, 0);
   b->start.assign(k, 0);
-  b->rule.assign(k, StopRule{opts->max_iter, opts->tol_gap, opts->tol_pri, opts->tol_dual});
+  b->rule.resize(k);
+  for (int j = 0; j < k; ++j) b->rule[j] = make_rule(*opts, opts->max_iter, b->rho[j]);
   b->rec.assign((size_t)k * kFinal, NAN);
   b->mask_words = (c->Np + 63) / 64;
 
@@ -628,6 +633,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, kp * sizeof(double))); b->wbot = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->n_iso * kp * sizeof(double))); b->bbot = (double *)p;
   B_RC(batch_alloc(b, &p, kp * sizeof(int32_t))); b->active = (int32_t *)p;
+  B_RC(batch_alloc(b, &p, kp * sizeof(double))); b->fac = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk1 * c->ntp * kp * Tsz)); b->P1 = p;
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->r = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk2 * c->mAp * kp * sizeof(double))); b->P2 = (double *)p;
@@ -644,6 +650,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)max_row_blocks * kObjStats * kp * sizeof(double))); b->obj_stats = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)kp * kFinal * sizeof(double))); b->fin = (double *)p;
   B_HIP(hipHostMalloc((void **)&b->h_fin, (size_t)kp * kFinal * sizeof(double), hipHostMallocDefault));
+  B_HIP(hipHostMalloc((void **)&b->h_fac, (size_t)kp * sizeof(double), hipHostMallocDefault));
   B_HIP(hipMemsetAsync(b->q, 0, (size_t)c->Np * kp * Tsz, b->stream));
   B_HIP(hipMemsetAsync(b->W, 0, (size_t)c->Np * kp * Tsz, b->stream));
   B_HIP(hipMemsetAsync(b->qs, 0, (size_t)c->n_sec * kp * sizeof(double), b->stream));
@@ -976,8 +983,46 @@ int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed_out) {
   return LADMM_OK;
 }
 
+int adapt_rho(ladmm_batch *b, bool *switched) {
+  ladmm_case *c = b->c;
+  bool any = false;
+  for (int j = 0; j < b->kp; ++j) b->h_fac[j] = 1.0;
+  for (int j = 0; j < b->k; ++j) {
+    const StopRule &r = b->rule[j];
+    if (!b->h_active[j] || !r.adapt) continue;
+    const double rp = b->rec[(size_t)j * kFinal + 3], rd = b->rec[(size_t)j * kFinal + 4];
+    double nr = b->rho[j];
+    if (rp > r.mu * rd) nr *= r.tau;
+    else if (rd > r.mu * rp) nr /= r.tau;
+    nr = std::min(std::max(nr, r.rho_lo), r.rho_hi);
+    if (nr == b->rho[j]) continue;
+    b->h_fac[j] = b->rho[j] / nr;
+    b->rho[j] = nr;
+    any = true;
+  }
+  if (switched) *switched = any;
+  if (!any) return LADMM_OK;
+  hipStream_t s = b->stream;
+  HIPC(hipMemcpyAsync(b->fac, b->h_fac, b->kp * sizeof(double), hipMemcpyHostToDevice, s));
+  SmallArgs sa = small_args(b);
+  HIPC(rescale_small(s, sa, b->q2, b->qs, b->invrho, b->fac));
+  if (c->precision == LADMM_F64) {
+    HIPC(rescale_points<double>(s, (double *)b->q, c->Np, b->kp, point_table<double>(b), b->fac));
+    HIPC(w_from_q<double>(s, (const double *)b->q, (double *)b->W, c->Np, b->kp, point_table<double>(b)));
+  } else {
+    HIPC(rescale_points<float>(s, (float *)b->q, c->Np, b->kp, point_table<float>(b), b->fac));
+    if (c->precision == LADMM_F32)
+      HIPC(w_from_q<float>(s, (const float *)b->q, (float *)b->W, c->Np, b->kp, point_table<float>(b)));
+    else
+      HIPC(w_from_q_bf(s, (const float *)b->q, c->Np, b->kp, point_table<float>(b), (uint16_t *)b->W,
+                       (uint16_t *)b->W + (size_t)b->kp * c->Np));
+  }
+  return LADMM_OK;
+}
+
 // Run n iterations (the last one with statistics), update the host records and,
-// if `decide`, freeze plans that meet their stopping rule.
+// if `decide`, freeze plans that meet their stopping rule and, after a full
+// check chunk, balance the step sizes of the plans that ask for it.
 int run_chunk(ladmm_batch *b, int n, bool decide) {
   if (n <= 0) return LADMM_OK;
   int rc = prepare_batch(b);
@@ -987,6 +1032,10 @@ int run_chunk(ladmm_batch *b, int n, bool decide) {
   bool changed = false;
   rc = chunk_complete(b, n, decide, &changed);
   if (rc) return rc;
+  if (decide && n == b->opts.check_every) {
+    rc = adapt_rho(b, nullptr);
+    if (rc) return rc;
+  }
   if (changed)
     HIPC(hipMemcpy(b->active, b->h_active.data(), b->kp * sizeof(int32_t), hipMemcpyHostToDevice));
   return LADMM_OK;

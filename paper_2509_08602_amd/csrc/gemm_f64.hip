@@ -24,6 +24,8 @@ template hipError_t gemm_tn<double>(hipStream_t, const double *, int, const doub
                                     int);
 template hipError_t gemm_nn<double>(hipStream_t, int, const double *, int, const double *, int,
                                     int, int, int, const EpiArgs<double> &, int);
+template hipError_t rescale_points<double>(hipStream_t, double *, int, int, const PointTable<double> &,
+                                          const double *);
 template hipError_t w_from_q<double>(hipStream_t, const double *, double *, int, int,
                                      const PointTable<double> &);
 }  // namespace ladmm

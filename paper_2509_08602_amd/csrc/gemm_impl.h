@@ -561,6 +561,28 @@ __global__ void k_w_from_q(const T *__restrict__ q, T *__restrict__ w, int Np, i
 }
 
 template <typename T>
+__global__ void k_rescale_points(T *__restrict__ q, int Np, int kp, PointTable<T> pt,
+                                 const double *__restrict__ fac) {
+  const size_t total = (size_t)Np * kp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / kp), j = (int)(e % kp);
+    const double f = fac[j];
+    if (f == 1.0) continue;
+    const T qv = q[e];
+    const T z = clip0u(qv, upper_of(pt, pt.grp[p], p, j));
+    q[e] = (T)((double)z + ((double)qv - (double)z) * f);
+  }
+}
+
+template <typename T>
+hipError_t rescale_points(hipStream_t s, T *q, int Np, int kp, const PointTable<T> &pt,
+                          const double *fac) {
+  hipLaunchKernelGGL((k_rescale_points<T>), dim3(2048), dim3(256), 0, s, q, Np, kp, pt, fac);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t w_from_q(hipStream_t s, const T *q, T *w, int Np, int kp, const PointTable<T> &pt) {
   hipLaunchKernelGGL((k_w_from_q<T>), dim3(2048), dim3(256), 0, s, q, w, Np, kp, pt);
   return hipGetLastError();

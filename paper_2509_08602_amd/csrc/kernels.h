@@ -150,6 +150,15 @@ hipError_t band_bits(hipStream_t s, const double *d, int ldd, int n_vox, int k, 
 template <typename T>
 hipError_t w_from_q(hipStream_t s, const T *q, T *w, int Np, int kp, const PointTable<T> &pt);
 
+// ---- step-size switch ------------------------------------------------------------
+// For every plan j with fac[j] != 1: y <- fac[j] y at fixed z (q = z + y) on
+// the dose points, the sector variables and the small rows, and 1/rho_j <-
+// fac[j] / rho_j (fac = rho_old / rho_new).
+template <typename T>
+hipError_t rescale_points(hipStream_t s, T *q, int Np, int kp, const PointTable<T> &pt, const double *fac);
+hipError_t rescale_small(hipStream_t s, const SmallArgs &a, double *q2, double *qs, double *invrho,
+                         const double *fac);
+
 // ---- state conversion ---------------------------------------------------------
 template <typename T>
 hipError_t export_points(hipStream_t s, const T *q, int ldq, const PointTable<T> &pt, int N, int k,

@@ -46,8 +46,8 @@ struct Request {
   int k = 0;
   std::vector<ladmm_weights> w;
   std::vector<uint64_t> mask;   // k x ceil(N/64) words; empty = every LD point
-  StopRule rule{};
-  double rho0 = 0.0, w0 = 0.0;
+  ladmm_opts opts{};
+  int32_t max_iter = 0;   // rounded up to a multiple of the server's check_every
   ladmm_result out{};
   // worker-owned
   int next = 0;        // plans admitted so far
@@ -157,7 +157,7 @@ void admit(Lane &L, int s, Request *r, int p) {
     set_u_column<double>(L, s, w, cnt);
   else
     set_u_column<float>(L, s, w, cnt);
-  const double rho = r->rho0 * std::sqrt(r->w0 / w.w_bot);
+  const double rho = r->opts.rho0 * std::sqrt(r->opts.w0_bot / w.w_bot);
   L.h_invrho[s] = 1.0 / rho;
   L.h_wbot[s] = w.w_bot;
   for (int i = 0; i < c->n_iso; ++i) L.h_bbot[(size_t)i * kp + s] = c->hE[c->ntp + i] * w.w_bot;
@@ -166,7 +166,7 @@ void admit(Lane &L, int s, Request *r, int p) {
   b->w[s] = w;
   b->rho[s] = rho;
   b->start[s] = b->iters_run;
-  b->rule[s] = r->rule;
+  b->rule[s] = make_rule(r->opts, r->max_iter, rho);
   b->status[s] = LADMM_PLAN_RUNNING;
   b->iters[s] = 0;
   std::fill(b->rec.begin() + (size_t)s * kFinal, b->rec.begin() + (size_t)(s + 1) * kFinal, NAN);
@@ -487,6 +487,14 @@ void worker_main(ladmm_server *sv) {
       const int active = L->b->chunk_active;
       int rc = chunk_complete(L->b, K, true, &changed);
       if (rc == LADMM_OK) rc = retire(sv, *L, &touched);
+      if (rc == LADMM_OK) {
+        // step-size balancing of the running plans; keep the table mirror in step
+        bool switched = false;
+        rc = adapt_rho(L->b, &switched);
+        if (rc == LADMM_OK && switched)
+          for (int s = 0; s < L->b->kp; ++s)
+            if (L->owner[s]) L->h_invrho[s] = 1.0 / L->b->rho[s];
+      }
       if (rc) {
         fail_lane(sv, L, rc, g_err, &finals);
         continue;
@@ -622,6 +630,9 @@ int ladmm_submit(ladmm_server *sv, ladmm_case *c, int32_t k, const ladmm_weights
   if (opts->check_every != 0 && opts->check_every != sv->opts.check_every)
     return fail(LADMM_E_INVALID, "submit: check_every must be 0 or the server's");
   if (!(opts->rho0 > 0) || !(opts->w0_bot > 0)) return fail(LADMM_E_INVALID, "submit: rho0 and w0_bot must be > 0");
+  if (opts->adapt_rho && (!(opts->adapt_mu > 1) || !(opts->adapt_tau > 1) ||
+                          !std::isfinite(opts->adapt_mu) || !std::isfinite(opts->adapt_tau)))
+    return fail(LADMM_E_INVALID, "submit: adapt_mu and adapt_tau must be finite and > 1");
   int rc = validate_weights(k, w);
   if (rc) return rc;
   Request *r = new Request();
@@ -629,9 +640,8 @@ int ladmm_submit(ladmm_server *sv, ladmm_case *c, int32_t k, const ladmm_weights
   r->w.assign(w, w + k);
   if (ld_mask) r->mask.assign(ld_mask, ld_mask + (size_t)k * ((c->N + 63) / 64));
   const int K = sv->opts.check_every;
-  r->rule = StopRule{(opts->max_iter + K - 1) / K * K, opts->tol_gap, opts->tol_pri, opts->tol_dual};
-  r->rho0 = opts->rho0;
-  r->w0 = opts->w0_bot;
+  r->opts = *opts;
+  r->max_iter = (opts->max_iter + K - 1) / K * K;
   r->out = *out;
   rc = case_ref(c);
   if (rc) {

@@ -602,6 +602,37 @@ hipError_t shot_times_matrix(hipStream_t s, const SmallArgs &a, const double *q2
   return hipGetLastError();
 }
 
+// Step-size switch on the small rows (z2 = min(q2, b): b = 0 on shot rows,
+// E_bot w_BOT on BOT rows) and the sector variables (z = max(qs, 0)).
+__global__ void k_rescale_small(SmallArgs a, double *__restrict__ q2, double *__restrict__ qs,
+                                double *__restrict__ invrho, const double *__restrict__ fac) {
+  const int kp = a.kp;
+  const size_t rows = (size_t)a.L.mAp + a.L.n_sec;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < rows * kp;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e / kp), j = (int)(e % kp);
+    const double f = fac[j];
+    if (f == 1.0) continue;
+    if (m < a.L.mAp) {
+      const bool bot = m >= a.L.ntp && m < a.L.ntp + a.L.n_iso;
+      const double bound = bot ? a.bbot[(size_t)(m - a.L.ntp) * kp + j] : 0.0;
+      const double v = q2[e], z = fmin(v, bound);
+      q2[e] = z + (v - z) * f;
+      if (m == 0) invrho[j] *= f;
+    } else {
+      const size_t i = e - (size_t)a.L.mAp * kp;
+      const double v = qs[i], z = fmax(v, 0.0);
+      qs[i] = z + (v - z) * f;
+    }
+  }
+}
+
+hipError_t rescale_small(hipStream_t s, const SmallArgs &a, double *q2, double *qs, double *invrho,
+                         const double *fac) {
+  hipLaunchKernelGGL(k_rescale_small, dim3(512), dim3(256), 0, s, a, q2, qs, invrho, fac);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // state conversion between q and the (z, y) pair of the oracle's variables
 // ---------------------------------------------------------------------------

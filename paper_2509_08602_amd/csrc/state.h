@@ -36,7 +36,16 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 struct StopRule {
   int32_t max_iter;
   double tol_gap, tol_pri, tol_dual;
+  // step-size balancing (adapt = 0: the fixed rule); rho kept in [rho_lo, rho_hi]
+  int32_t adapt;
+  double mu, tau, rho_lo, rho_hi;
 };
+
+// The stopping and step-size rule of a plan that starts with step size rho.
+inline StopRule make_rule(const ladmm_opts &o, int32_t max_iter, double rho) {
+  return StopRule{max_iter, o.tol_gap, o.tol_pri, o.tol_dual, o.adapt_rho, o.adapt_mu, o.adapt_tau,
+                  rho * 1e-3, rho * 1e3};
+}
 
 }  // namespace ladmm
 
@@ -91,6 +100,8 @@ struct ladmm_batch {
   void *utab = nullptr;       // (G + 1) x kp (T)
   uint64_t *mask = nullptr;   // kp x mask_words
   double *invrho = nullptr, *bbot = nullptr, *wbot = nullptr;
+  double *fac = nullptr;      // kp: scaled-dual factor rho_old / rho_new of a switch
+  double *h_fac = nullptr;    // pinned kp
   int32_t *active = nullptr;
   void *P1 = nullptr;
   double *r = nullptr, *P2 = nullptr, *v = nullptr;
@@ -148,6 +159,10 @@ int chunk_launch(ladmm_batch *b, int n);
 // Wait for the chunk, update per-plan records, and with `decide` apply each
 // plan's stopping rule.  Frozen plans get h_active = 0; *changed reports any.
 int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed);
+// Step-size balancing after a full check chunk (decide): new rho of the
+// running plans that ask for it, and the rescale of their scaled duals on the
+// batch's stream.  *switched reports any change.
+int adapt_rho(ladmm_batch *b, bool *switched);
 // tau_i = (phi_cal/D_T) max_s sum_c t_isc for one plan's shot times.
 void bot_from_t(const ladmm_case *c, const double *t, double *bot);
 

@@ -53,7 +53,8 @@ class _Weights(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("tol_gap", C.c_double),
                 ("tol_pri", C.c_double), ("tol_dual", C.c_double), ("rho0", C.c_double),
-                ("w0_bot", C.c_double), ("autotune", C.c_int32)]
+                ("w0_bot", C.c_double), ("autotune", C.c_int32), ("adapt_rho", C.c_int32),
+                ("adapt_mu", C.c_double), ("adapt_tau", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -187,14 +188,18 @@ class Options:
     tol_gap: float = 1e-4
     tol_pri: float = 1e-4
     tol_dual: float = 1e-4
-    rho0: float = 1000.0
+    rho0: float = 1e4          # the rule's constant, tuned on the synthetic generator
     w0_bot: float = 1e-3
     autotune: bool = True
+    adapt_rho: bool = True
+    adapt_mu: float = 10.0
+    adapt_tau: float = 2.0
 
     def c(self):
         return _Opts(int(self.max_iter), int(self.check_every), float(self.tol_gap),
                      float(self.tol_pri), float(self.tol_dual), float(self.rho0),
-                     float(self.w0_bot), 1 if self.autotune else 0)
+                     float(self.w0_bot), 1 if self.autotune else 0, 1 if self.adapt_rho else 0,
+                     float(self.adapt_mu), float(self.adapt_tau))
 
 
 class Context:

@@ -114,6 +114,7 @@ int main(int argc, char **argv) {
   if (solve_iters > 0) {
     ladmm_opts so = o;
     so.max_iter = solve_iters; so.check_every = 5; so.tol_gap = 1e-6; so.tol_pri = 1e-6; so.tol_dual = 1e-6;
+    so.adapt_rho = 1; so.adapt_mu = 1.5; so.adapt_tau = 2.0;   // step-size switches at every check
     CHECK(ladmm_solve_batch(cs, k, w.data(), use_mask ? mask.data() : nullptr, &so, &r));
   }
   }

@@ -76,7 +76,7 @@ def test_iterations_match_oracle_c0(ctx, c0, precision, tol1, tol50):
     w = cases.config_weights(0)
     _, slp, rho = oracle_setup(c0, w)
     dc = ladmm.Case.from_case(ctx, c0, precision)
-    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
     fac, _ = oadmm.schur_factor(slp)
     st = None
     done = 0
@@ -98,7 +98,7 @@ def test_import_export_roundtrip_and_resume(ctx, c0):
     fac, _ = oadmm.schur_factor(slp)
     st = oadmm.admm_iterate(slp, rho, 37, factor=fac)
     dc = ladmm.Case.from_case(ctx, c0, "f64")
-    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
     b.load(st.z1, st.y1, st.z2, st.y2)
     z1, y1, z2, y2 = b.export()
     assert rel_err(z1, st.z1) < 1e-15 and rel_err(y2, st.y2) < 1e-15
@@ -124,7 +124,7 @@ def test_solve_matches_exact_optimum_c0(ctx, c0):
     lp, slp, rho = oracle_setup(c0, w)
     dc = ladmm.Case.from_case(ctx, c0, "f64")
     opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
-                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False)
     b = ladmm.Batch(dc, w, opts=opts)
     b.run()
     res = b.results()
@@ -175,7 +175,7 @@ def test_ld_mask_iteration_parity(ctx, c0):
         mask[j, ld[rng.random(ld.size) < rng.uniform(0.2, 0.9)]] = True
     _, slp, rho = oracle_setup(c0, w, ld_mask=mask)
     dc = ladmm.Case.from_case(ctx, c0, "f64")
-    b = ladmm.Batch(dc, w, ld_mask=mask, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
+    b = ladmm.Batch(dc, w, ld_mask=mask, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
     b.iterate(20)
     st = oadmm.admm_iterate(slp, rho, 20)
     z1, y1, z2, y2 = b.export()
@@ -192,7 +192,7 @@ def test_oar_case_solve(ctx):
     w = cases.random_weights(5, 3)
     lp, slp, rho = oracle_setup(case, w)
     dc = ladmm.Case.from_case(ctx, case, "f64")
-    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
     b.iterate(30)
     st = oadmm.admm_iterate(slp, rho, 30)
     z1, y1, z2, y2 = b.export()
@@ -240,7 +240,7 @@ def test_iteration_parity_c1(ctx, c1, precision):
     w = cases.config_weights(1)
     _, slp, rho = oracle_setup(c1, w)
     dc = ladmm.Case.from_case(ctx, c1, precision)
-    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT))
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
     b.iterate(3)
     st = oadmm.admm_iterate(slp, rho, 3)
     z1, y1, z2, y2 = b.export()
@@ -261,7 +261,7 @@ def test_solve_c1_sampled_exact(ctx, c1, precision):
     w = cases.config_weights(1)
     dc = ladmm.Case.from_case(ctx, c1, precision)
     opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
-                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False)
     res = ladmm.solve_batch(dc, w, opts=opts)
     rel = {j: abs(res["objective"][j] - f) / f for j, f in fs.items()}
     say("c1", precision, "sampled objective rel err", rel, "iters", res["iters"][list(fs)])
@@ -303,7 +303,7 @@ def test_solve_bf16x3_matches_exact_optimum_c0(ctx, c0):
     w = cases.config_weights(0)
     dc = ladmm.Case.from_case(ctx, c0, "bf16x3")
     opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
-                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False)
     res = ladmm.solve_batch(dc, w, opts=opts)
     fs = golden_fstar(0)
     Fstar = np.array([fs[j] for j in range(w.shape[0])])
@@ -312,3 +312,44 @@ def test_solve_bf16x3_matches_exact_optimum_c0(ctx, c0):
     rel = np.abs(res["objective"] - Fstar) / Fstar
     say("c0 bf16x3 objective rel err", rel, "iters", res["iters"])
     assert np.all(rel < 1e-3), rel
+
+
+def test_adaptive_rho_matches_oracle_c0(ctx, c0):
+    """Step-size balancing (FP64): after 300 iterations with a check every 50,
+    the device's step sizes equal the oracle's, and so do z and the
+    multipliers rho * y (invariant under a switch)."""
+    say("adaptive rho parity c0 f64")
+    w = cases.config_weights(0)
+    _, slp, rho = oracle_setup(c0, w)
+    dc = ladmm.Case.from_case(ctx, c0, "f64")
+    opts = ladmm.Options(max_iter=300, check_every=50, tol_gap=0.0, rho0=1000.0,
+                         w0_bot=cases.W0_BOT, adapt_rho=True, adapt_mu=10.0, adapt_tau=2.0)
+    b = ladmm.Batch(dc, w, opts=opts)
+    b.run()
+    z1, y1, z2, y2 = b.export()
+    res = b.results()
+    st, rho_end = oadmm.admm_adaptive(slp, rho, 300, 50)
+    # the device freezes plans at max_iter before the last balancing step:
+    # compare the step sizes through the iterate they produced, t = E rho y2
+    t_orc, _ = oadmm.shot_times(slp, rho_end, st)
+    assert rel_err(res["t"].T, t_orc) < 1e-9
+    assert rel_err(z1, st.z1) < 1e-9 and rel_err(z2, st.z2) < 1e-9
+    assert np.any(rho_end != rho)
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_tuned_default_step_rule_reaches_exact_optimum_c1(ctx, c1, precision):
+    """The library's default step rule (rho0 = 1e4 from a grid over 30..1e4 on
+    the synthetic generator, with residual balancing) brings the sampled plans
+    of the medium case within 1e-3 of their exact optimum."""
+    say("solve c1 default step rule", precision)
+    fs = golden_fstar(1)
+    w = cases.config_weights(1)
+    dc = ladmm.Case.from_case(ctx, c1, precision)
+    opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
+                         tol_dual=1e-4, w0_bot=cases.W0_BOT)
+    res = ladmm.solve_batch(dc, w, opts=opts)
+    rel = {j: abs(res["objective"][j] - f) / f for j, f in fs.items()}
+    say("c1", precision, "default rule rel err", rel, "iters", res["iters"][list(fs)],
+        "max iters", res["iters"].max())
+    assert all(v < 1e-3 for v in rel.values()), rel

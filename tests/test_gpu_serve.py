@@ -48,9 +48,9 @@ def mini():
     return cases.build_case(spec, 11)
 
 
-def opts(max_iter, tol=1e-4, K=50):
+def opts(max_iter, tol=1e-4, K=50, adapt=True):
     return ladmm.Options(max_iter=max_iter, check_every=K, tol_gap=tol, tol_pri=tol, tol_dual=tol,
-                         rho0=1000.0, w0_bot=cases.W0_BOT, autotune=False)
+                         rho0=1000.0, w0_bot=cases.W0_BOT, autotune=False, adapt_rho=adapt)
 
 
 def same(a, b):
@@ -67,7 +67,7 @@ def test_served_plans_equal_plans_solved_alone(ctx, c0, mini):
     dm = ladmm.Case.from_case(ctx, mini, "f64")
     w0 = cases.config_weights(0)
     wr = cases.random_weights(40, 3)
-    o, oR = opts(1000), opts(8000)
+    o, oR = opts(1000), opts(8000, adapt=False)   # R: the paper's fixed step rule
     alone_R = ladmm.solve_batch(d0, w0, opts=oR)
     alone_m = [ladmm.solve_batch(dm, wr[i:i + 8], opts=o) for i in range(0, 40, 8)]
     alone_1 = ladmm.solve_batch(d0, wr[5:6], opts=o)

@@ -37,7 +37,7 @@ def test_two_pass_c0_matches_oracle():
     d_ld, delta = 0.5 * case.prescription_mean, 0.1 * case.prescription_mean
     n_ld = np.full(k, 500)
     opts = ladmm.Options(max_iter=8000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
-                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+                         tol_dual=1e-4, rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False)
     ctx = ladmm.Context(0)
     r1, r2, P, n2, times = ladmm.two_pass(ctx, case, w, phi, d_ld, delta, n_ld, 12345, ld_group,
                                           "f64", opts)

@@ -105,3 +105,45 @@ def test_admm_converges_to_simplex_optimum():
     assert np.all(gap < 1e-2)
     r_pri, r_dual = admm.residuals(slp, rho, st)
     assert np.all(r_pri < 1e-3) and np.all(r_dual < 1e-3)
+
+
+def test_adaptive_rho_switch_keeps_the_multipliers():
+    """A step-size switch rescales the scaled duals so that rho * y (the
+    multipliers, hence the shot times t = E rho y2) is unchanged, and with
+    balancing disabled the adaptive run is the plain iteration, bitwise."""
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    slp = olp.precondition(olp.assemble(case, w), olp.bot_scale(case))
+    rho = olp.rho_rule(w[:, 3], 1000.0, cases.W0_BOT)
+    fac, _ = admm.schur_factor(slp)
+    plain = admm.admm_iterate(slp, rho, 50, factor=fac)
+    st, rho_new = admm.admm_adaptive(slp, rho, 50, 50, factor=fac)
+    assert np.any(rho_new != rho)                    # some plan switched at the check
+    assert np.all(np.isin(rho_new / rho, [0.5, 1.0, 2.0]))
+    assert np.array_equal(st.z1, plain.z1) and np.array_equal(st.z2, plain.z2)
+    assert np.array_equal(rho_new * st.y2, rho * plain.y2)
+    assert np.array_equal(rho_new * st.y1, rho * plain.y1)
+    off, rho_off = admm.admm_adaptive(slp, rho, 120, 50, mu=np.inf, factor=fac)
+    ref = admm.admm_iterate(slp, rho, 120, factor=fac)
+    assert np.array_equal(rho_off, rho)
+    assert np.array_equal(off.y2, ref.y2) and np.array_equal(off.z1, ref.z1)
+
+
+def test_adaptive_rho_recovers_from_a_poor_start():
+    """Started 30x below the tuned step size, residual balancing brings every
+    plan within 3e-3 of its exact optimum (c0, 9 plans) in 3,000 iterations,
+    several times closer than the fixed step size gets."""
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    lp = olp.assemble(case, w)
+    Fstar = np.array([-solve_plan(lp, j).objective for j in range(w.shape[0])])
+    slp = olp.precondition(lp, olp.bot_scale(case))
+    rho = olp.rho_rule(w[:, 3], 30.0, cases.W0_BOT)
+    fac, _ = admm.schur_factor(slp)
+    st, rho_end = admm.admm_adaptive(slp, rho, 3000, 50, factor=fac)
+    F = olp.planning_objective(case, w, admm.shot_times(slp, rho_end, st)[0])[0]
+    fixed = admm.admm_iterate(slp, rho, 3000, factor=fac)
+    F_fixed = olp.planning_objective(case, w, admm.shot_times(slp, rho, fixed)[0])[0]
+    err, err_fixed = np.abs(F - Fstar) / Fstar, np.abs(F_fixed - Fstar) / Fstar
+    assert np.all(err < 3e-3), err
+    assert err_fixed.max() > 5 * err.max()
