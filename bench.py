@@ -143,6 +143,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--launch", default="graph", choices=("graph", "eager"),
+                    help="timed region: replayed HIP graphs of each check chunk, or one-by-one launches")
     return ap.parse_args()
 
 
@@ -188,20 +190,29 @@ def uneven(args):
         sizes.append((c.n_points, c.n_t))
         del c
     w = cases.config_weights(1)
-    srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
     fixed = lambda n: ladmm.Options(max_iter=n, check_every=ITERS_PER_STEP, tol_gap=0.0,
                                     rho0=RHO0, w0_bot=cases.W0_BOT)
-    for t in [srv.submit(dc, w, opts=fixed(ITERS_PER_STEP)) for dc in dcs]:   # lanes + tiles
-        t.wait()
-    t0 = time.perf_counter()
-    ts = [srv.submit(dc, w, opts=fixed(iters)) for dc in dcs]
-    for t in ts:
-        t.wait()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
+
+    def run(eager):
+        srv = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True, eager=eager)
+        for t in [srv.submit(dc, w, opts=fixed(ITERS_PER_STEP)) for dc in dcs]:   # lanes + tiles
+            t.wait()
+        t0 = time.perf_counter()
+        ts = [srv.submit(dc, w, opts=fixed(iters)) for dc in dcs]
+        for t in ts:
+            t.wait()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return wall, st
+
     k = w.shape[0]
+    wall, st = run(args.launch == "eager")
+    other_wall, _ = run(args.launch != "eager")
     value = n_cases * k * iters / wall
+    other = n_cases * k * iters / other_wall
+    launch = dict(mode=args.launch, plan_iterations_per_s={
+        args.launch: round(value, 1), ("eager" if args.launch == "graph" else "graph"): round(other, 1)})
     flops = sum(4.0 * N * nt * k for N, nt in sizes) * iters
     print(json.dumps({
         "metric": "plan-iterations/s", "value": round(value, 1), "unit": "plan-iterations/s",
@@ -213,6 +224,7 @@ def uneven(args):
                                f"{max(s[1] for s in sizes)}), {k} plans each, f32, served "
                                f"together", "cases": n_cases, "plans_per_case": k,
                    "iterations": iters, "setup_ms_total": round(setup, 1)},
+        "launch": launch,
         "dose_product_tflops": round(flops / wall / 1e12, 2),
         "lanes": st["lanes"], "hbm_gb": round(ctx.used_bytes / 1e9, 2)}))
 
@@ -318,20 +330,35 @@ def main():
     fixed = ladmm.Options(max_iter=ITERS_PER_STEP, check_every=ITERS_PER_STEP, tol_gap=0.0,
                           rho0=rho0, w0_bot=cases.W0_BOT)
     b = ladmm.Batch(dc, w, opts=fixed)
+
+    def timed(steps):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.iterate(ITERS_PER_STEP)     # synchronous: returns after the check is read back
+        return time.perf_counter() - t0
+
+    # timed region: each step replays the captured graph of one check chunk
+    b.set_graphs(args.launch == "graph")
     for _ in range(args.warmup):
         b.iterate(ITERS_PER_STEP)
+    wall = timed(args.steps)
+    # kernel durations: HIP events around every launch on the batch's stream
+    # (this launches kernel by kernel), the same number of steps right after
     b.set_profiling(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        b.iterate(ITERS_PER_STEP)     # synchronous: returns after the check is read back
-    wall = time.perf_counter() - t0
+    wall_prof = timed(args.steps)
     ktimes = b.kernel_times()
-    tiles = b.tiles()
     b.set_profiling(False)
+    # one-by-one launches without events, for the launch-mode comparison
+    b.set_graphs(False)
+    wall_eager = timed(args.steps)
+    tiles = b.tiles()
     res = b.results(with_t=False)
     b.close()
     ms_per_step = wall * 1000.0 / args.steps
     value = k * ITERS_PER_STEP * args.steps / wall
+    launch_modes = {"graph" if args.launch == "graph" else "eager_timed": round(value, 1),
+                    "eager": round(k * ITERS_PER_STEP * args.steps / wall_eager, 1),
+                    "eager_with_kernel_events": round(k * ITERS_PER_STEP * args.steps / wall_prof, 1)}
 
     # roofline of the dominant kernel (by accumulated device time): the
     # product's flops for the k plans (2 N n_t k per MFMA pass) per launch
@@ -391,6 +418,7 @@ def main():
                    "points": N, "shots": n_t, "plans": k,
                    "iterations_per_step": ITERS_PER_STEP, "setup_ms": round(setup_ms, 2),
                    "tiles": {"gemm1": tiles[0], "gemm2": tiles[1]}},
+        "launch": dict(mode=args.launch, plan_iterations_per_s=launch_modes),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -221,6 +221,14 @@ int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2);
  * An index that is not valid for the batch's shapes falls back to 0.
  * LADMM_E_INVALID for an index outside [0, 4). */
 int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2);
+/* Launch mode of the iterations of the stacked plans (end of Sec. 2.B).  With
+ * graphs on (the default) the kernel launches of a run chunk (check_every
+ * iterations, the last with statistics) are captured once per chunk length and
+ * tile configuration into a HIP graph on the batch's stream and replayed for
+ * every later chunk; off, they are launched one by one.  Both
+ * run the same kernels on the same arguments, so results are identical.
+ * Profiling always launches one by one.  Graphs are destroyed with the batch. */
+int ladmm_batch_set_graphs(ladmm_batch *b, int32_t on);
 int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
 int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
 
@@ -311,12 +319,15 @@ int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
  *                retirement happen between chunks.  >= 1.
  *   max_lanes:   at most this many cases hold lane memory at once (0: no limit
  *                besides the HBM budget).
- *   autotune:    time the tile configurations when a lane is created. */
+ *   autotune:    time the tile configurations when a lane is created.
+ *   eager:       nonzero: launch each lane's kernels one by one instead of
+ *                replaying a captured graph per chunk (ladmm_batch_set_graphs). */
 typedef struct {
   int32_t slots;
   int32_t check_every;
   int32_t max_lanes;
   int32_t autotune;
+  int32_t eager;
 } ladmm_server_opts;
 
 /* Counters of a server.  Latencies (submit to final status, completed requests

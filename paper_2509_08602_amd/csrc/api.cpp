@@ -460,6 +460,7 @@ void case_unref(ladmm_case *c) {
 int destroy_batch_impl(ladmm_batch *b) {
   if (!b) return LADMM_OK;
   if (b->stream) hipStreamSynchronize(b->stream);
+  for (auto &g : b->graph_cache) hipGraphExecDestroy(g.exec);
   for (hipEvent_t e : b->ev_pool) hipEventDestroy(e);
   for (void *p : b->allocs) hipFree(p);
   ctx_release(b->c->ctx, b->bytes);
@@ -928,14 +929,54 @@ int prepare_batch(ladmm_batch *b) {
   return LADMM_OK;
 }
 
+// Enqueue n iterations (the last with statistics).  Outside profiling the
+// launches are captured once into a HIP graph and replayed: every kernel
+// argument is a pointer or a size fixed for the batch's life except the tile
+// configurations, which key the graph together with n.  Frozen plans, new
+// step sizes and new slots change only device memory the kernels read.
+int enqueue_iterations(ladmm_batch *b, int n) {
+  if (b->profiling || !b->graphs) {
+    for (int i = 0; i < n; ++i) {
+      int rc = iterate_any(b, i == n - 1);
+      if (rc) return rc;
+    }
+    return LADMM_OK;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (const auto &g : b->graph_cache)
+    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2) exec = g.exec;
+  if (!exec) {
+    HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LADMM_OK;
+    for (int i = 0; i < n && rc == LADMM_OK; ++i) rc = iterate_any(b, i == n - 1);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (rc == LADMM_OK && e != hipSuccess)
+      rc = fail(LADMM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    if (rc == LADMM_OK) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = fail(LADMM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    if (graph) hipGraphDestroy(graph);
+    if (rc) return rc;
+    // a handful of chunk lengths per batch at most (the check interval and a
+    // shorter last chunk); keep the four most recent
+    if (b->graph_cache.size() == 4) {
+      hipGraphExecDestroy(b->graph_cache.front().exec);
+      b->graph_cache.erase(b->graph_cache.begin());
+    }
+    b->graph_cache.push_back({n, b->cfg1, b->cfg2, exec});
+  }
+  HIPC(hipGraphLaunch(exec, b->stream));
+  return LADMM_OK;
+}
+
 int chunk_launch(ladmm_batch *b, int n) {
   b->chunk_active = 0;
   for (int j = 0; j < b->k; ++j) b->chunk_active += b->h_active[j] != 0;
   HIPC(hipEventRecord(b->ev0, b->stream));
-  for (int i = 0; i < n; ++i) {
-    int rc = iterate_any(b, i == n - 1);
-    if (rc) return rc;
-  }
+  int rc = enqueue_iterations(b, n);
+  if (rc) return rc;
   HIPC(hipEventRecord(b->ev1, b->stream));
   HIPC(hipMemcpyAsync(b->h_fin, b->fin, (size_t)b->kp * kFinal * sizeof(double),
                       hipMemcpyDeviceToHost, b->stream));
@@ -1306,6 +1347,12 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const
   }
   HIPC(hipMemcpy(b->qs, qs.data(), qs.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(b->q2, q2.data(), q2.size() * sizeof(double), hipMemcpyHostToDevice));
+  return LADMM_OK;
+}
+
+int ladmm_batch_set_graphs(ladmm_batch *b, int32_t on) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  b->graphs = on != 0;
   return LADMM_OK;
 }
 

@@ -233,6 +233,7 @@ int make_lane(ladmm_server *sv, ladmm_case *c, std::unique_ptr<Lane> *out) {
   int rc = create_batch_impl(c, sv->opts.slots, nullptr, nullptr, nullptr, &o, &L->b, true);
   if (rc) return rc;
   ladmm_batch *b = L->b;
+  b->graphs = sv->opts.eager == 0;
   const int kp = b->kp;
   const size_t Tsz = c->precision == LADMM_F64 ? sizeof(double) : sizeof(float);
   L->owner.assign(kp, nullptr);

@@ -126,6 +126,10 @@ struct ladmm_batch {
   // tile configurations of the two dose-matrix products (autotuned)
   int cfg1 = 0, cfg2 = 0;
   bool tuned = false;
+  // captured iteration chunks, replayed while profiling is off
+  struct Graph { int n, cfg1, cfg2; hipGraphExec_t exec; };
+  bool graphs = true;
+  std::vector<Graph> graph_cache;
   // per-kernel event timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;

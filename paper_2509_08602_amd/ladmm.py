@@ -75,7 +75,7 @@ class _Result(C.Structure):
 
 class _ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("check_every", C.c_int32), ("max_lanes", C.c_int32),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("eager", C.c_int32)]
 
 
 class _ServerStats(C.Structure):
@@ -125,6 +125,7 @@ _SIGS = {
     "ladmm_batch_export": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
+    "ladmm_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_tiles": (C.c_int, [C.c_void_p, _IP, _IP]),
     "ladmm_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -382,6 +383,10 @@ class Batch:
     def set_tiles(self, gemm1, gemm2):
         _check(library().ladmm_batch_set_tiles(self._h, int(gemm1), int(gemm2)))
 
+    def set_graphs(self, on=True):
+        """Replay captured HIP graphs of each run chunk (default) or launch one by one."""
+        _check(library().ladmm_batch_set_graphs(self._h, 1 if on else 0))
+
     def set_profiling(self, on=True):
         _check(library().ladmm_batch_set_profiling(self._h, 1 if on else 0))
 
@@ -554,12 +559,13 @@ class Server:
     """Continuous-batching server (ladmm_server_*): requests of k plans on resident cases."""
 
     def __init__(self, ctx: Context, slots: int = 96, check_every: int = 50, max_lanes: int = 0,
-                 autotune: bool = True):
+                 autotune: bool = True, eager: bool = False):
         self.ctx = ctx
         self.check_every = int(check_every)
         self._h = C.c_void_p()
         self._live = {}
-        o = _ServerOpts(int(slots), int(check_every), int(max_lanes), 1 if autotune else 0)
+        o = _ServerOpts(int(slots), int(check_every), int(max_lanes), 1 if autotune else 0,
+                        1 if eager else 0)
         _check(library().ladmm_server_create(ctx._h, C.byref(o), C.byref(self._h)))
         _SERVERS.add(self)
 

@@ -180,6 +180,21 @@ hipError_t hipEventRecord(hipEvent_t, hipStream_t);
 hipError_t hipEventSynchronize(hipEvent_t);
 hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t);
 
+// Stream capture: kernel launches of the capturing thread are recorded into the
+// graph and run, in order, at each hipGraphLaunch.  Any other stream operation
+// while capturing is an error here, so a copy, fill or event that slipped into
+// a captured region fails the emulated run.
+typedef struct hostemu_graph *hipGraph_t;
+typedef struct hostemu_graph *hipGraphExec_t;
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal,
+                            hipStreamCaptureModeRelaxed };
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode);
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *);
+hipError_t hipGraphInstantiate(hipGraphExec_t *, hipGraph_t, void *, char *, size_t);
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGraphDestroy(hipGraph_t);
+hipError_t hipGraphExecDestroy(hipGraphExec_t);
+
 #define hipLaunchKernelGGL(K, G, B, SH, S, ...)                    \
   do {                                                            \
     (void)(SH);                                                   \

@@ -55,7 +55,23 @@ void *wave_slot(size_t bytes) {
 }
 void *peer_slot(int linear_tid) { return (*g_fibers)[linear_tid].slot; }
 
+}  // namespace hostemu
+
+struct hostemu_graph {
+  struct Node { dim3 grid, block; std::function<void()> body; };
+  std::vector<Node> nodes;
+};
+
+namespace hostemu {
+namespace {
+thread_local hostemu_graph *g_capture = nullptr;
+}
+
 void launch(dim3 grid, dim3 block, std::function<void()> body) {
+  if (g_capture) {
+    g_capture->nodes.push_back({grid, block, std::move(body)});
+    return;
+  }
   gridDim_ = grid;
   blockDim_ = block;
   const int nthr = (int)(block.x * block.y * block.z);
@@ -112,14 +128,47 @@ hipError_t hipFree(void *p) { free(p); return hipSuccess; }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) { return hipMalloc(p, n); }
 hipError_t hipHostFree(void *p) { free(p); return hipSuccess; }
 hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { memmove(d, s, n); return hipSuccess; }
-hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) { return hipMemcpy(d, s, n, k); }
-hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { memset(d, v, n); return hipSuccess; }
+hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+  if (hostemu::g_capture) return hipErrorInvalidValue;
+  return hipMemcpy(d, s, n, k);
+}
+hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
+  if (hostemu::g_capture) return hipErrorInvalidValue;
+  memset(d, v, n);
+  return hipSuccess;
+}
 hipError_t hipStreamCreate(hipStream_t *s) { *s = (hipStream_t)0x1; return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
-hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t) { return hostemu::g_capture ? hipErrorInvalidValue : hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t *e) { *e = new hostemu_event(); return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->t = std::chrono::steady_clock::now(); return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
+  if (hostemu::g_capture) return hipErrorInvalidValue;
+  e->t = std::chrono::steady_clock::now();
+  return hipSuccess;
+}
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) {
+  if (hostemu::g_capture) return hipErrorInvalidValue;
+  hostemu::g_capture = new hostemu_graph();
+  return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
+  if (!hostemu::g_capture) return hipErrorInvalidValue;
+  *g = hostemu::g_capture;
+  hostemu::g_capture = nullptr;
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t g, void *, char *, size_t) {
+  *e = new hostemu_graph(*g);
+  return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  if (hostemu::g_capture) return hipErrorInvalidValue;
+  for (auto &n : e->nodes) hostemu::launch(n.grid, n.block, n.body);
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete e; return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
   *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();

@@ -92,10 +92,12 @@ def test_served_plans_equal_plans_solved_alone(ctx, c0, mini):
         assert abs(F[j] - fs) <= 1e-3 * abs(fs) + 1e-9, (j, F[j], fs)
 
 
-@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
-def test_slot_reuse_and_masks_match_alone(ctx, mini, precision):
-    """More plans than slots (plans start in freed slots), with LD masks."""
-    say("serve slot reuse mini", precision)
+@pytest.mark.parametrize("precision,eager", [("f32", False), ("bf16x3", False), ("f32", True)])
+def test_slot_reuse_and_masks_match_alone(ctx, mini, precision, eager):
+    """More plans than slots (plans start in freed slots), with LD masks.  The
+    lanes replay captured graphs (or, eager, launch one by one); the requests
+    solved alone replay graphs."""
+    say("serve slot reuse mini", precision, "eager" if eager else "graphs")
     dm = ladmm.Case.from_case(ctx, mini, precision)
     k = 70
     w = cases.random_weights(k, 6)
@@ -106,7 +108,7 @@ def test_slot_reuse_and_masks_match_alone(ctx, mini, precision):
     for j in range(k):
         mask[j, ld[rng.random(ld.size) < 0.7]] = True
     reqs = [(0, 30, 200), (30, 31, 400), (31, 70, 100)]
-    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=True)
+    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=True, eager=eager)
     tickets = [srv.submit(dm, w[a:b], ld_mask=mask[a:b], opts=opts(m, tol=0.0)) for a, b, m in reqs]
     for (a, b, m), t in zip(reqs, tickets):
         ref = ladmm.solve_batch(dm, w[a:b], ld_mask=mask[a:b], opts=opts(m, tol=0.0))
