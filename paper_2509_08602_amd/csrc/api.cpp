@@ -896,7 +896,7 @@ int autotune(ladmm_batch *b) {
   HIPC(hipMalloc((void **)&noact, kp * sizeof(int32_t)));
   hipError_t e = hipMemsetAsync(noact, 0, kp * sizeof(int32_t), s);
   float best1 = 1e30f, best2 = 1e30f;
-  for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
+  for (int cfg = 0; cfg < kMaxGemmCfgs && e == hipSuccess; ++cfg) {
     for (int which = 0; which < 2 && e == hipSuccess; ++which) {
       if (!cfg_ok(b, which, cfg)) continue;
       float tot = 0.f;
@@ -1384,7 +1384,7 @@ int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2) {
 
 int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
-  if (gemm1 < 0 || gemm1 >= kGemmCfgs || gemm2 < 0 || gemm2 >= kGemmCfgs)
+  if (gemm1 < 0 || gemm1 >= kMaxGemmCfgs || gemm2 < 0 || gemm2 >= kMaxGemmCfgs)
     return fail(LADMM_E_INVALID, "tile configuration out of range");
   b->cfg1 = cfg_ok(b, 0, gemm1) ? gemm1 : 0;
   b->cfg2 = cfg_ok(b, 1, gemm2) ? gemm2 : 0;

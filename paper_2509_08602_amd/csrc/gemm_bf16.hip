@@ -8,11 +8,18 @@
 // x-update of Eq. (partial_elimination) at close to FP32 accuracy on the BF16
 // matrix cores; the Schur complement solve and the small side stay FP64.
 //
-// Layout: both operands row-major with the reduction index contiguous, so a
-// lane's fragment (8 consecutive k of one row) is one 16-byte LDS read.
 // MFMA 16x16x32 bf16 operand layout (gfx950, checked by a lane probe): lane l
 // supplies A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and
 // receives D[4 (l / 16) + r][l % 16] in accumulator register r.
+//
+// Layouts.  The dose block (operand A of both products) is stored in fragment
+// order: for every 16-row tile and every 32-wide k step, the 64 lanes' 16-byte
+// pieces (lane l: row l % 16, k 8 (l / 16) .. + 8) are consecutive, so a
+// fragment is 1 KiB of contiguous HBM and a wavefront loads it with one fully
+// coalesced 16-byte-per-lane instruction (frag_off gives the offsets).
+// The plan-side operand B (W, v_top, the scaled shot times) is plan-major with
+// the reduction index contiguous; both are staged through LDS as rows with the
+// k index contiguous, so a lane's fragment is one 16-byte LDS read.
 #include "kernels.h"
 
 #include <math.h>
@@ -50,6 +57,13 @@ __device__ __forceinline__ int xcd_tile_bf(int id, int total) {
   return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
 }
 
+// Element offset of the 16-byte piece (row, k .. k + 7), k % 8 == 0, of an
+// M x K operand in fragment order (K % 32 == 0).
+__host__ __device__ __forceinline__ size_t frag_off(int row, int k, int K) {
+  return ((size_t)(row >> 4) * (size_t)(K >> 5) + (size_t)(k >> 5)) * 512 +
+         (size_t)((((k & 31) >> 3) << 4) | (row & 15)) * 8;
+}
+
 __device__ __forceinline__ float upper_bf(const PointTable<float> &pt, int g, int p, int j) {
   float u = pt.utab[(size_t)g * pt.ldu + j];
   if (pt.mask != nullptr && pt.is_ld[g]) {
@@ -59,142 +73,37 @@ __device__ __forceinline__ float upper_bf(const PointTable<float> &pt, int g, in
   return u;
 }
 
-constexpr int kBfBK = 32;              // one MFMA k-step per stage
+constexpr int kBfBK = 32;              // one MFMA k-step
 constexpr int kBfLd = kBfBK + 8;       // LDS row: 80 bytes, 8 rows cover all banks
 
-// MODE 0: split-K partial store; otherwise the NN epilogue EPI_ADMM / _STATS / _OBJ.
-// NBUF: 2 = double-buffered LDS stages; 1 = one stage (half the LDS, so more
-// workgroups per CU), the next stage waiting in registers behind a barrier.
-template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, int K, int kchunk,
-                                                         int mtiles, int ntiles,
-                                                         float *__restrict__ P, int ldp,
-                                                         size_t pstride, EpiArgs<float> ea) {
+template <int MODE>
+constexpr int bf_nstat() { return MODE == EPI_OBJ ? kObjStats : kAdmmStats; }
+template <int MODE>
+constexpr bool bf_has_stats() { return MODE == EPI_ADMM_STATS || MODE == EPI_OBJ; }
+// LDS of the statistics partials: one per 16-row tile, statistic and column.
+template <int BM, int BN, int MODE>
+constexpr size_t bf_red_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
+
+__device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
+
+// After the k loop, shared by both kernels.  MODE 0: the split-K partial
+// store; otherwise the point-row epilogue EPI_ADMM / _STATS / _OBJ with the
+// same arithmetic as the FP32 path and W' written plan-major as pairs.
+// Statistics: per 16-row tile, every lane sums its 4 rows, two shuffles combine
+// the 4 lanes of a column, and the two tiles of each 32-row block are added
+// (one partial per 32-row block).  `smem` must hold bf_red_bytes and no wave
+// may still read operand tiles from it.
+template <int BM, int BN, int WM, int WN, int MODE>
+__device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 * WN)],
+                                            unsigned char *smem, int tid, int mt, int m0, int n0,
+                                            int zc, float *__restrict__ P, int ldp, size_t pstride,
+                                            const EpiArgs<float> &ea) {
   constexpr int NT = 64 * WM * WN;
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
-  static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
-  static_assert(MODE == 0 || BM % 32 == 0, "statistics partials are per 32-row block");
-  constexpr int KV = kBfBK / 8;                        // 16-byte vectors per row slice
-  constexpr int AV = BM * KV, BV = BN * KV;
-  constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;
-  constexpr bool ALO = TERMS == 3;
-  constexpr int NST = (MODE == EPI_OBJ) ? kObjStats : kAdmmStats;
-  constexpr bool kStats = MODE == EPI_ADMM_STATS || MODE == EPI_OBJ;
-  constexpr int T16 = BM / 16;
-  constexpr size_t kTileA = sizeof(uint16_t) * NBUF * BM * kBfLd;
-  constexpr size_t kTileB = sizeof(uint16_t) * NBUF * BN * kBfLd;
-  constexpr size_t kBytesT = kTileA * (ALO ? 2 : 1) + kTileB * 2;
-  constexpr size_t kBytesR = kStats ? sizeof(double) * T16 * NST * BN : 0;
-  constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  auto sAh = reinterpret_cast<uint16_t (*)[BM][kBfLd]>(smem);
-  auto sBh = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileA);
-  auto sBl = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileA + kTileB);
-  auto sAl = reinterpret_cast<uint16_t (*)[BM][kBfLd]>(smem + kTileA + 2 * kTileB);
-  auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NST = bf_nstat<MODE>();
+  constexpr bool kStats = bf_has_stats<MODE>();
+  const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  // tile order: column blocks fastest (they share the row slab of A), then
-  // row tiles (which share a split-K chunk of B), then chunks
-  const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
-  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
-  const int m0 = mt * BM, n0 = nt * BN;
-  const int kbeg = MODE == 0 ? zc * kchunk : 0;
-  const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
-
-  f4v acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
-
-  uint4 rah[AVT], ral[ALO ? AVT : 1], rbh[BVT], rbl[BVT];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < AVT; ++i) {
-      const int e = tid + i * NT;
-      if (e < AV) {
-        const int row = e / KV, k = k0 + (e % KV) * 8;
-        const size_t off = (size_t)(m0 + row) * A.ld + k;
-        rah[i] = k < kend ? *reinterpret_cast<const uint4 *>(A.hi + off) : uint4{0, 0, 0, 0};
-        if (ALO) ral[i] = k < kend ? *reinterpret_cast<const uint4 *>(A.lo + off) : uint4{0, 0, 0, 0};
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < BVT; ++i) {
-      const int e = tid + i * NT;
-      if (e < BV) {
-        const int row = e / KV, k = k0 + (e % KV) * 8;
-        const size_t off = (size_t)(n0 + row) * B.ld + k;
-        rbh[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
-        rbl[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < AVT; ++i) {
-      const int e = tid + i * NT;
-      if (e < AV) {
-        const int row = e / KV, kv = (e % KV) * 8;
-        *reinterpret_cast<uint4 *>(&sAh[buf][row][kv]) = rah[i];
-        if (ALO) *reinterpret_cast<uint4 *>(&sAl[buf][row][kv]) = ral[i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < BVT; ++i) {
-      const int e = tid + i * NT;
-      if (e < BV) {
-        const int row = e / KV, kv = (e % KV) * 8;
-        *reinterpret_cast<uint4 *>(&sBh[buf][row][kv]) = rbh[i];
-        *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[i];
-      }
-    }
-  };
-
-  if (kbeg < kend) {
-    load(kbeg);
-    store(0);
-    __syncthreads();
-    int buf = 0;
-    const int g8 = 8 * (lane >> 4), r16 = lane & 15;
-    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
-      const bool more = k0 + kBfBK < kend;
-      if (more) load(k0 + kBfBK);
-      bf8v ah[TM], al[ALO ? TM : 1], bh[TN], bl[TN];
-#pragma unroll
-      for (int tm = 0; tm < TM; ++tm) {
-        const int row = wm * TM * 16 + tm * 16 + r16;
-        ah[tm] = *reinterpret_cast<const bf8v *>(&sAh[buf][row][g8]);
-        if (ALO) al[tm] = *reinterpret_cast<const bf8v *>(&sAl[buf][row][g8]);
-      }
-#pragma unroll
-      for (int tn = 0; tn < TN; ++tn) {
-        const int row = wn * TN * 16 + tn * 16 + r16;
-        bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][row][g8]);
-        bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][row][g8]);
-      }
-#pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
-#pragma unroll
-        for (int tn = 0; tn < TN; ++tn) {
-          acc[tm][tn] = mfma_bf(ah[tm], bh[tn], acc[tm][tn]);
-          acc[tm][tn] = mfma_bf(ah[tm], bl[tn], acc[tm][tn]);
-          if (ALO) acc[tm][tn] = mfma_bf(al[tm], bh[tn], acc[tm][tn]);
-        }
-      if (NBUF == 2) {
-        if (more) store(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-      } else {
-        __syncthreads();          // every wave has read the stage
-        if (more) store(0);
-        __syncthreads();
-      }
-    }
-  }
-
   if (MODE == 0) {
     float *Pz = P + (size_t)zc * pstride;
 #pragma unroll
@@ -209,11 +118,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
         }
     return;
   }
-
-  // Epilogue on the point-row product: the same arithmetic as the FP32 path,
-  // with W' written plan-major as pairs.  Statistics: per 16-row tile, every
-  // lane sums its 4 rows, two shuffles combine the 4 lanes of a column, and the
-  // two tiles of each 32-row block are added (one partial per 32-row block).
+  auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -269,7 +174,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
             uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
       }
       if (kStats) {
-        // the operand tiles are no longer read: every wave passed the last barrier
 #pragma unroll
         for (int q = 0; q < NST; ++q) {
           double v = st[q];
@@ -294,15 +198,292 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
   }
 }
 
-// Tile configurations (rows BM, columns BN, wavefront grid WM x WN, LDS
-// stages) of the split-K product (which = 0) and the point-row product (1).
-struct BfCfg { int bm, bn, wm, wn, nbuf; };
-static const BfCfg kBfCfgs[2][kGemmCfgs] = {
-    {{64, 32, 2, 1, 2}, {64, 64, 2, 1, 1}, {64, 64, 4, 1, 1}, {128, 64, 4, 1, 1}},
-    {{64, 32, 2, 1, 2}, {128, 32, 4, 1, 1}, {128, 64, 4, 1, 1}, {256, 64, 4, 1, 1}}};
+// Both operands staged through LDS.  MODE 0: split-K partial store; otherwise
+// the NN epilogue.  NBUF: 2 = double-buffered LDS stages; 1 = one stage (half
+// the LDS, so more workgroups per CU), the next stage waiting in registers
+// behind a barrier.
+template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, int K, int kchunk,
+                                                         int mtiles, int ntiles,
+                                                         float *__restrict__ P, int ldp,
+                                                         size_t pstride, EpiArgs<float> ea) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
+  static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "tile shape");
+  static_assert(MODE == 0 || BM % 32 == 0, "statistics partials are per 32-row block");
+  constexpr int KV = kBfBK / 8;                        // 16-byte vectors per row slice
+  constexpr int AV = BM * KV, BV = BN * KV;
+  constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;
+  constexpr bool ALO = TERMS == 3;
+  constexpr size_t kTileA = sizeof(uint16_t) * NBUF * BM * kBfLd;
+  constexpr size_t kTileB = sizeof(uint16_t) * NBUF * BN * kBfLd;
+  constexpr size_t kBytesT = kTileA * (ALO ? 2 : 1) + kTileB * 2;
+  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE>();
+  constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  auto sAh = reinterpret_cast<uint16_t (*)[BM][kBfLd]>(smem);
+  auto sBh = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileA);
+  auto sBl = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileA + kTileB);
+  auto sAl = reinterpret_cast<uint16_t (*)[BM][kBfLd]>(smem + kTileA + 2 * kTileB);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  // tile order: column blocks fastest (they share the row slab of A), then
+  // row tiles (which share a split-K chunk of B), then chunks
+  const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
+  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = MODE == 0 ? zc * kchunk : 0;
+  const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
+
+  f4v acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  // A pieces: 64 consecutive threads take one fragment (1 KiB contiguous)
+  static_assert(KV == 4, "one fragment per 16 rows and k step");
+  auto a_row = [](int e) { return (e >> 6) * 16 + (e & 15); };
+  auto a_kv = [](int e) { return ((e & 63) >> 4) * 8; };
+  uint4 rah[AVT], ral[ALO ? AVT : 1], rbh[BVT], rbl[BVT];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        const int k = k0 + a_kv(e);
+        const size_t off = frag_off(m0 + a_row(e), k, A.ld);
+        rah[i] = k < kend ? *reinterpret_cast<const uint4 *>(A.hi + off) : uint4{0, 0, 0, 0};
+        if (ALO) ral[i] = k < kend ? *reinterpret_cast<const uint4 *>(A.lo + off) : uint4{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int row = e / KV, k = k0 + (e % KV) * 8;
+        const size_t off = (size_t)(n0 + row) * B.ld + k;
+        rbh[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
+        rbl[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < AV) {
+        *reinterpret_cast<uint4 *>(&sAh[buf][a_row(e)][a_kv(e)]) = rah[i];
+        if (ALO) *reinterpret_cast<uint4 *>(&sAl[buf][a_row(e)][a_kv(e)]) = ral[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int row = e / KV, kv = (e % KV) * 8;
+        *reinterpret_cast<uint4 *>(&sBh[buf][row][kv]) = rbh[i];
+        *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[i];
+      }
+    }
+  };
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    const int g8 = 8 * (lane >> 4), r16 = lane & 15;
+    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
+      const bool more = k0 + kBfBK < kend;
+      if (more) load(k0 + kBfBK);
+      bf8v ah[TM], al[ALO ? TM : 1], bh[TN], bl[TN];
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) {
+        const int row = wm * TM * 16 + tm * 16 + r16;
+        ah[tm] = *reinterpret_cast<const bf8v *>(&sAh[buf][row][g8]);
+        if (ALO) al[tm] = *reinterpret_cast<const bf8v *>(&sAl[buf][row][g8]);
+      }
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const int row = wn * TN * 16 + tn * 16 + r16;
+        bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][row][g8]);
+        bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][row][g8]);
+      }
+      // term-major: TM TN independent products between two on one accumulator
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(ah[tm], bh[tn], acc[tm][tn]);
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(ah[tm], bl[tn], acc[tm][tn]);
+      if (ALO) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(al[tm], bh[tn], acc[tm][tn]);
+      }
+      if (NBUF == 2) {
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      } else {
+        __syncthreads();          // every wave has read the stage
+        if (more) store(0);
+        __syncthreads();
+      }
+    }
+  }
+  bf_epilogue<BM, BN, WM, WN, MODE>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+}
+
+// Direct-A variant.  The waves split the rows only, so the rows of A a wave
+// multiplies are its own: each lane loads its A fragments straight from global
+// memory into registers in the MFMA operand layout; only B, which every wave
+// reads, is staged through LDS (two stages).  Global loads of both operands are
+// issued PD stages ahead into a register ring, so PD k-steps of MFMA work cover
+// the latency of a load.  Per k-step and tile: the same three products in the
+// same order as k_gemm_bf, so both kernels give the same bits.  LDS traffic per
+// k-step and wave: 2 TN fragment reads for 3 TM TN MFMAs, against 2 (TM + TN)
+// with A staged too.
+template <int TM, int TN, int WM, int PD, int TERMS, int MODE>
+__global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K, int kchunk,
+                                                      int mtiles, int ntiles,
+                                                      float *__restrict__ P, int ldp,
+                                                      size_t pstride, EpiArgs<float> ea) {
+  constexpr int BM = TM * 16 * WM, BN = TN * 16, NT = 64 * WM;
+  constexpr int KV = kBfBK / 8;
+  constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
+  constexpr bool ALO = TERMS == 3;
+  constexpr int TA = ALO ? TM : 1;
+  static_assert(PD >= 1, "prefetch distance");
+  static_assert(MODE == 0 || (TM * 16) % 32 == 0, "statistics partials are per 32-row block");
+  constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
+  constexpr size_t kBytesT = 2 * kTileB;
+  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE>();
+  constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  auto sBh = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem);
+  auto sBl = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileB);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
+  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = MODE == 0 ? zc * kchunk : 0;
+  const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
+  const int g8 = 8 * (lane >> 4), r16 = lane & 15;
+
+  f4v acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  // register ring: slot 0 holds the stage being multiplied, slot p the stage p
+  // ahead.  A fragment of 16-row tile t at k step k0 / 32: 1 KiB at
+  // frag_off(16 t, k0, K); this lane's piece is 8 lane elements further.
+  const size_t arow = frag_off(m0 + wave * TM * 16, 0, A.ld) + (size_t)lane * 8;
+  const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
+  uint4 ah[PD + 1][TM], al[PD + 1][TA], rbh[PD + 1][BVT], rbl[PD + 1][BVT];
+  auto load = [&](int k0, int slot) {
+    const bool in = k0 + g8 < kend;
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) {
+      const size_t off = arow + tm * astep + (size_t)(k0 >> 5) * 512;
+      ah[slot][tm] = in ? *reinterpret_cast<const uint4 *>(A.hi + off) : uint4{0, 0, 0, 0};
+      if (ALO) al[slot][tm] = in ? *reinterpret_cast<const uint4 *>(A.lo + off) : uint4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int row = e / KV, k = k0 + (e % KV) * 8;
+        const size_t off = (size_t)(n0 + row) * B.ld + k;
+        rbh[slot][i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
+        rbl[slot][i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
+      }
+    }
+  };
+  auto store_b = [&](int slot, int buf) {
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int row = e / KV, kv = (e % KV) * 8;
+        *reinterpret_cast<uint4 *>(&sBh[buf][row][kv]) = rbh[slot][i];
+        *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[slot][i];
+      }
+    }
+  };
+
+  if (kbeg < kend) {
+#pragma unroll
+    for (int p = 0; p < PD; ++p)
+      if (kbeg + p * kBfBK < kend) load(kbeg + p * kBfBK, p);
+    store_b(0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
+      if (k0 + PD * kBfBK < kend) load(k0 + PD * kBfBK, PD);
+      bf8v bh[TN], bl[TN];
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][tn * 16 + r16][g8]);
+        bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][tn * 16 + r16][g8]);
+      }
+      // term-major: TM TN independent products between two on one accumulator
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), bh[tn], acc[tm][tn]);
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), bl[tn], acc[tm][tn]);
+      if (ALO) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+          for (int tn = 0; tn < TN; ++tn)
+            acc[tm][tn] = mfma_bf(as_bf8(al[0][ALO ? tm : 0]), bh[tn], acc[tm][tn]);
+      }
+      const bool more = k0 + kBfBK < kend;
+      if (more) store_b(1, buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+#pragma unroll
+      for (int p = 0; p < PD; ++p) {
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) ah[p][tm] = ah[p + 1][tm];
+#pragma unroll
+        for (int tm = 0; tm < TA; ++tm) al[p][tm] = al[p + 1][tm];
+#pragma unroll
+        for (int i = 0; i < BVT; ++i) {
+          rbh[p][i] = rbh[p + 1][i];
+          rbl[p][i] = rbl[p + 1][i];
+        }
+      }
+    }
+  }
+  bf_epilogue<BM, BN, WM, 1, MODE>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+}
+
+// Tile configurations of the split-K product (which = 0) and the point-row
+// product (1): rows BM x columns BN of a workgroup, staged (both operands
+// through LDS, k_gemm_bf) or direct (A from global memory, k_gemm_bfd).
+// Configuration 0 is valid for every padded shape (M % 64, N % 32).
+constexpr int kBfCfgCount = 6;
+struct BfCfg { int bm, bn; };
+static const BfCfg kBfCfgs[2][kBfCfgCount] = {
+    {{64, 32}, {64, 64}, {192, 112}, {160, 112}, {64, 96}, {192, 64}},
+    {{64, 32}, {256, 64}, {128, 112}, {128, 112}, {128, 96}, {128, 64}}};
 
 bool gemm_bf_cfg_ok(int which, int cfg, int M, int N) {
-  if (cfg < 0 || cfg >= kGemmCfgs) return false;
+  if (cfg < 0 || cfg >= kBfCfgCount) return false;
   const BfCfg c = kBfCfgs[which][cfg];
   return M % c.bm == 0 && N % c.bn == 0;
 }
@@ -314,27 +495,35 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
   const BfCfg c = kBfCfgs[MODE == 0 ? 0 : 1][cfg];
   const int mtiles = M / c.bm, ntiles = N / c.bn;
   const dim3 grid(mtiles * ntiles * nchunk);
-#define BF_ONE(BMv, BNv, WMv, WNv, NB)                                                             \
+#define BF_ST(BMv, BNv, WMv, WNv, NB)                                                              \
   hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE, NB>), grid, dim3(64 * WMv * WNv), 0, \
                      s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
-  if (MODE == 0) {
+#define BF_DI(TMv, TNv, WMv)                                                                       \
+  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, TERMS, MODE>), grid, dim3(64 * WMv), 0, s, A, B, \
+                     K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
+  if constexpr (MODE == 0) {
     switch (cfg) {
-      case 0: BF_ONE(64, 32, 2, 1, 2); break;
-      case 1: BF_ONE(64, 64, 2, 1, 1); break;
-      case 2: BF_ONE(64, 64, 4, 1, 1); break;
-      case 3: BF_ONE(128, 64, 4, 1, 1); break;
+      case 0: BF_ST(64, 32, 2, 1, 2); break;
+      case 1: BF_ST(64, 64, 2, 1, 1); break;
+      case 2: BF_DI(3, 7, 4); break;
+      case 3: BF_DI(5, 7, 2); break;
+      case 4: BF_DI(1, 6, 4); break;
+      case 5: BF_DI(3, 4, 4); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (cfg) {
-      case 0: BF_ONE(64, 32, 2, 1, 2); break;
-      case 1: BF_ONE(128, 32, 4, 1, 1); break;
-      case 2: BF_ONE(128, 64, 4, 1, 1); break;
-      case 3: BF_ONE(256, 64, 4, 1, 1); break;
+      case 0: BF_ST(64, 32, 2, 1, 2); break;
+      case 1: BF_ST(256, 64, 4, 1, 1); break;
+      case 2: BF_DI(2, 7, 4); break;
+      case 3: BF_DI(4, 7, 2); break;
+      case 4: BF_DI(2, 6, 4); break;
+      case 5: BF_DI(2, 4, 4); break;
       default: return hipErrorInvalidValue;
     }
   }
-#undef BF_ONE
+#undef BF_ST
+#undef BF_DI
   return hipGetLastError();
 }
 
@@ -370,46 +559,65 @@ hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, 
 // ---------------------------------------------------------------------------
 // operand preparation
 // ---------------------------------------------------------------------------
-// Point-major pairs: one thread per element, coalesced along shots.
-__global__ void k_split_dose(const double *__restrict__ Dt, const double *__restrict__ E, int Np,
-                             int ntp, uint16_t *__restrict__ Dh, uint16_t *__restrict__ Dl) {
-  const size_t total = (size_t)Np * ntp;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int t = (int)(e % ntp);
+// D^ = Dt diag(E) as pairs in fragment order, for both products at once: a
+// workgroup converts a 64-point x 64-shot tile in LDS and writes the 8
+// fragments it holds of the point-major block (16-point tiles x 32-shot steps,
+// the point-row product's operand) and the 8 of the shot-major block (16-shot
+// tiles x 32-point steps, the split-K product's operand), 1 KiB each,
+// coalesced.  Np % 64 == 0 and ntp % 64 == 0.
+__global__ __launch_bounds__(256) void k_split_dose_frag(const double *__restrict__ Dt,
+                                                         const double *__restrict__ E, int Np,
+                                                         int ntp, uint16_t *__restrict__ Dh,
+                                                         uint16_t *__restrict__ Dl,
+                                                         uint16_t *__restrict__ DTh,
+                                                         uint16_t *__restrict__ DTl) {
+  __shared__ uint16_t sh[64][66], sl[64][66];   // [point][shot]
+  const int t0 = blockIdx.x * 64, p0 = blockIdx.y * 64, tid = threadIdx.x;
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int pp = i >> 6, tt = i & 63;
     uint16_t h, l;
-    split_pair(Dt[e] * E[t], h, l);
-    Dh[e] = h;
-    Dl[e] = l;
-  }
-}
-
-// Shot-major copy through a 64 x 64 LDS tile.
-__global__ void k_transpose_u16(const uint16_t *__restrict__ in, int rows, int cols,
-                                uint16_t *__restrict__ out) {
-  __shared__ uint16_t tile[64][65];
-  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-  for (int i = threadIdx.y; i < 64; i += blockDim.y) {
-    const int r = r0 + i, c = c0 + threadIdx.x;
-    tile[i][threadIdx.x] = (r < rows && c < cols) ? in[(size_t)r * cols + c] : 0;
+    split_pair(Dt[(size_t)(p0 + pp) * ntp + t0 + tt] * E[t0 + tt], h, l);
+    sh[pp][tt] = h;
+    sl[pp][tt] = l;
   }
   __syncthreads();
-  for (int i = threadIdx.y; i < 64; i += blockDim.y) {
-    const int c = c0 + i, r = r0 + threadIdx.x;
-    if (c < cols && r < rows) out[(size_t)c * rows + r] = tile[threadIdx.x][i];
+  // 8 fragments x 64 lanes per block; lane L of a fragment: row L % 16, k 8 (L / 16) + e
+  for (int piece = tid; piece < 8 * 64; piece += 256) {
+    const int f = piece >> 6, L = piece & 63, r = L & 15, k8 = (L >> 4) * 8;
+    {  // point-major: rows = points, k = shots
+      const int pt = f >> 1, ts = f & 1;
+      const int pp = pt * 16 + r, tt = ts * 32 + k8;
+      uint16_t vh[8], vl[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        vh[e] = sh[pp][tt + e];
+        vl[e] = sl[pp][tt + e];
+      }
+      const size_t o = frag_off(p0 + pp, t0 + tt, ntp);
+      *reinterpret_cast<uint4 *>(Dh + o) = *reinterpret_cast<const uint4 *>(vh);
+      *reinterpret_cast<uint4 *>(Dl + o) = *reinterpret_cast<const uint4 *>(vl);
+    }
+    {  // shot-major: rows = shots, k = points
+      const int tt0 = f >> 1, ps = f & 1;
+      const int tt = tt0 * 16 + r, pp = ps * 32 + k8;
+      uint16_t vh[8], vl[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        vh[e] = sh[pp + e][tt];
+        vl[e] = sl[pp + e][tt];
+      }
+      const size_t o = frag_off(t0 + tt, p0 + pp, Np);
+      *reinterpret_cast<uint4 *>(DTh + o) = *reinterpret_cast<const uint4 *>(vh);
+      *reinterpret_cast<uint4 *>(DTl + o) = *reinterpret_cast<const uint4 *>(vl);
+    }
   }
 }
 
 hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int Np, int ntp,
                            uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl) {
-  hipLaunchKernelGGL(k_split_dose, dim3(4096), dim3(256), 0, s, Dt, E, Np, ntp, Dh, Dl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const dim3 grid((ntp + 63) / 64, (Np + 63) / 64);
-  hipLaunchKernelGGL(k_transpose_u16, grid, dim3(64, 4), 0, s, Dh, Np, ntp, DTh);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_transpose_u16, grid, dim3(64, 4), 0, s, Dl, Np, ntp, DTl);
+  if (Np % 64 || ntp % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split_dose_frag, dim3(ntp / 64, Np / 64), dim3(256), 0, s, Dt, E, Np, ntp, Dh,
+                     Dl, DTh, DTl);
   return hipGetLastError();
 }
 

@@ -180,7 +180,8 @@ hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int 
 // C = A B' with the ADMM / statistics / objective epilogues (W' written as pairs)
 hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
                       const EpiArgs<float> &ea, int terms, int cfg);
-// D^ = Dt diag(E) as pairs, point-major (Np x ntp) and shot-major (ntp x Np).
+// D^ = Dt diag(E) as pairs in fragment order (16-row tiles x 32-wide k steps,
+// 1 KiB per fragment), point-major (Np x ntp) and shot-major (ntp x Np).
 hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int Np, int ntp,
                            uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl);
 // v_top and the scaled shot times as plan-major pairs (kp x ntp) for the products.

@@ -277,23 +277,32 @@ def test_tile_configurations_give_identical_results(ctx, c0, precision):
     the same iterates and the same statistics, bit for bit (the configurations
     split the work but never reorder a floating-point sum)."""
     say("tile independence", precision)
-    w = cases.config_weights(0)
     dc = ladmm.Case.from_case(ctx, c0, precision)
     opts = ladmm.Options(max_iter=100, check_every=50, tol_gap=0.0, rho0=1000.0,
                          w0_bot=cases.W0_BOT, autotune=False)
-    ref = None
-    for c1 in range(4):
-        for c2 in range(4):
-            b = ladmm.Batch(dc, w, opts=opts)
-            b.set_tiles(c1, c2)
-            b.run()
-            res = b.results()
-            b.close()
-            if ref is None:
-                ref = res
-                continue
-            for key, val in res.items():
-                assert np.array_equal(val, ref[key]), (c1, c2, key)
+    # plan counts whose padded widths (32, 96, 448 columns) admit every BF16
+    # configuration at least once; the FP32 / FP64 tables have four
+    plan_sets = [cases.config_weights(0)]
+    ncfg = 4
+    if precision == "bf16x3":
+        plan_sets += [cases.config_weights(1), cases.config_weights(2)]
+        ncfg = 6
+    for w in plan_sets:
+        ref, used = None, set()
+        for c1 in range(ncfg):
+            for c2 in range(ncfg):
+                b = ladmm.Batch(dc, w, opts=opts)
+                b.set_tiles(c1, c2)
+                used.add(b.tiles())
+                b.run()
+                res = b.results()
+                b.close()
+                if ref is None:
+                    ref = res
+                    continue
+                for key, val in res.items():
+                    assert np.array_equal(val, ref[key]), (w.shape[0], c1, c2, key)
+        say("  plans", w.shape[0], "tile pairs run", sorted(used))
 
 
 def test_solve_bf16x3_matches_exact_optimum_c0(ctx, c0):
