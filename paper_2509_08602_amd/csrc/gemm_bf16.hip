@@ -119,6 +119,25 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
     return;
   }
   auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
+  // per-row (group, sign) and per-column (1/rho, active) values, loaded once
+  int grow[TM][4];
+  float srow[TM][4];
+#pragma unroll
+  for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * TM * 16 + tm * 16 + 4 * (lane >> 4) + r;
+      grow[tm][r] = ea.pt.grp[m];
+      srow[tm][r] = ea.pt.sig[m];
+    }
+  float irc[TN];
+  bool act[TN];
+#pragma unroll
+  for (int tn = 0; tn < TN; ++tn) {
+    const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
+    irc[tn] = MODE == EPI_OBJ ? 0.f : (float)ea.invrho[n];
+    act[tn] = MODE == EPI_OBJ ? false : ea.active[n] != 0;
+  }
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -129,11 +148,16 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
 #pragma unroll
       for (int q = 0; q < NST; ++q) st[q] = 0.0;
       uint16_t wh[4] = {0, 0, 0, 0}, wl[4] = {0, 0, 0, 0};
+      float qv4[4];
+      if (MODE != EPI_OBJ) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qv4[r] = ea.q[(size_t)(mb + r) * ea.ldq + n];
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = mb + r;
-        const int g = ea.pt.grp[m];
-        const float sg = ea.pt.sig[m];
+        const int g = grow[tm][r];
+        const float sg = srow[tm][r];
         const float u = upper_bf(ea.pt, g, m, n);
         const float s = acc[tm][tn][r];
         if (MODE == EPI_OBJ) {
@@ -144,13 +168,12 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
             st[0] = fma((double)u, h, st[0]);
           }
         } else {
-          float *qp = ea.q + (size_t)m * ea.ldq + n;
-          const float qv = *qp;
+          const float qv = qv4[r];
           const float z = clip0u_f(qv, u);
-          const float qn = z + sg * (float)ea.invrho[n] - s;
+          const float qn = z + sg * irc[tn] - s;
           const float wv = 2.f * clip0u_f(qn, u) - qn;
           split_pair((double)wv, wh[r], wl[r]);
-          if (ea.active[n]) *qp = qn;
+          if (act[tn]) ea.q[(size_t)m * ea.ldq + n] = qn;
           if (MODE == EPI_ADMM_STATS) {
             const double yo = (double)qv - (double)z;
             const double zn = (double)clip0u_f(qn, u);
@@ -166,7 +189,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           }
         }
       }
-      if (MODE != EPI_OBJ && ea.active[n]) {
+      if (MODE != EPI_OBJ && act[tn]) {
         const size_t o = (size_t)n * ea.ldwt + mb;
         *reinterpret_cast<uint2 *>(ea.wt_hi + o) =
             uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
