@@ -143,6 +143,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--warm-store", type=int, default=256,
+                    help="serving: solved plans kept per case for warm starts (0: cold starts)")
     ap.add_argument("--launch", default="graph", choices=("graph", "eager"),
                     help="timed region: replayed HIP graphs of each check chunk, or one-by-one launches")
     return ap.parse_args()
@@ -263,10 +265,17 @@ def serve(args):
 
     reqs = [draw() for _ in range(args.requests)]   # the same sequence at every level
 
+    warm = args.warm_store
+
     def run(load_rps, n):
         arr = np.random.default_rng(2001)
         gaps = arr.exponential(1.0 / load_rps, size=n) if load_rps else np.zeros(n)
-        s = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True)
+        s = ladmm.Server(ctx, slots=96, check_every=ITERS_PER_STEP, autotune=True, warm_store=warm)
+        if warm:
+            # solved weightings already in the store: the 3x3 slider grid of every case
+            for t in [s.submit(dc, grids[9], opts=opts) for dc in dcs]:
+                t.wait()
+        s.reset_stats()
         t0 = time.perf_counter()
         due, ts = t0, []
         for (ci, w), g in zip(reqs, gaps):
@@ -284,7 +293,7 @@ def serve(args):
         return dict(requests=n, plans=plans, seconds=round(wall, 3), p50_ms=round(st["p50_ms"], 2),
                     p99_ms=round(st["p99_ms"], 2), max_ms=round(st["max_ms"], 2),
                     plan_iterations_per_s=round(st["plan_iterations"] / wall, 1),
-                    completed=st["completed"])
+                    completed=st["completed"], warm_starts=st["warm_starts"])
 
     cal = run(0.0, args.requests)
     capacity = cal["requests"] / cal["seconds"]
@@ -300,8 +309,11 @@ def serve(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"serving: {n_cases} resident uneven cases, Poisson arrivals of "
-                               "1/9/81/441-plan requests (p 0.5/0.3/0.15/0.05), 1e-3 gap, "
-                               "cold start", "cases": n_cases, "requests_per_level": args.requests},
+                               "1/9/81/441-plan requests (p 0.5/0.3/0.15/0.05), 1e-3 gap, " +
+                               (f"warm start from the nearest solved weighting (store of {warm} "
+                                "plans per case, seeded with the 3x3 slider grid)" if warm else
+                                "cold start"), "cases": n_cases, "requests_per_level": args.requests,
+                   "warm_store": warm},
         "capacity_rps": round(capacity, 4), "closed_loop": cal, "levels": levels,
         "hbm_gb": round(ctx.used_bytes / 1e9, 2)}))
 

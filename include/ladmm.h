@@ -315,6 +315,18 @@ int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
  * a request that cannot fit even on an otherwise empty device fails with
  * LADMM_E_NOMEM.
  *
+ * Warm starts (warm_store > 0): each lane keeps the final iterates of up to
+ * warm_store converged plans of its case in HBM (charged to the budget, oldest
+ * replaced first).  A newly admitted plan then starts from the stored plan with
+ * the nearest weighting instead of from zero: its q = z + y, z2 + y2 and sector
+ * columns are copied, z and y follow from its own bounds, and it takes the
+ * stored plan's final step size.  The distance is Euclidean over (w_t, w_r,
+ * w_ld, log10(w_BOT) / 3), the slider coordinates of a weighting.  ADMM
+ * converges from any start, so a warm-started plan reaches the same optimum in
+ * fewer iterations; its result matches the plan solved alone within the
+ * stopping tolerance, not bitwise.  With warm_store = 0 every plan starts cold
+ * and the bitwise statement above holds.
+ *
  *   slots:       plan columns per lane, rounded up to a multiple of 32; [1, 4096].
  *   check_every: iterations per chunk; admission, the stopping test and
  *                retirement happen between chunks.  >= 1.
@@ -322,22 +334,25 @@ int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
  *                besides the HBM budget).
  *   autotune:    time the tile configurations when a lane is created.
  *   eager:       nonzero: launch each lane's kernels one by one instead of
- *                replaying a captured graph per chunk (ladmm_batch_set_graphs). */
+ *                replaying a captured graph per chunk (ladmm_batch_set_graphs).
+ *   warm_store:  solved plans kept per lane for warm starts; [0, 65536]. */
 typedef struct {
   int32_t slots;
   int32_t check_every;
   int32_t max_lanes;
   int32_t autotune;
   int32_t eager;
+  int32_t warm_store;
 } ladmm_server_opts;
 
 /* Counters of a server.  Latencies (submit to final status, completed requests
  * only) are nearest-rank percentiles in milliseconds; busy_ms is the wall time
  * of worker rounds that ran at least one lane; plan_iterations counts every
- * iteration of every occupied slot. */
+ * iteration of every occupied slot; warm_starts counts plans admitted from a
+ * stored plan. */
 typedef struct {
   int64_t submitted, completed, cancelled, failed;
-  int64_t plans_completed, plan_iterations;
+  int64_t plans_completed, plan_iterations, warm_starts;
   double p50_ms, p99_ms, max_ms, mean_ms, busy_ms;
   int32_t lanes, busy_slots;
 } ladmm_server_stats;
@@ -376,6 +391,9 @@ int ladmm_wait(ladmm_server *s, uint64_t ticket, int64_t timeout_us);
  * also when the request is already final. */
 int ladmm_cancel(ladmm_server *s, uint64_t ticket);
 int ladmm_server_get_stats(ladmm_server *s, ladmm_server_stats *out);
+/* Zero the counters and the latency record (lanes, stores and queued work are
+ * kept), e.g. after a warm-up phase. */
+int ladmm_server_reset_stats(ladmm_server *s);
 
 /* Message for the last error returned on this thread ("" if none). */
 const char *ladmm_last_error(void);

@@ -99,20 +99,6 @@ int batch_alloc(ladmm_batch *b, void **p, size_t bytes) {
   return rc;
 }
 
-template <typename T>
-PointTable<T> point_table(const ladmm_batch *b) {
-  const ladmm_case *c = b->c;
-  PointTable<T> pt;
-  pt.grp = c->grp;
-  pt.sig = (const T *)c->sig;
-  pt.is_ld = c->is_ld;
-  pt.is_oar = c->is_oar;
-  pt.utab = (const T *)b->utab;
-  pt.ldu = b->kp;
-  pt.mask = b->mask;
-  pt.mask_words = b->mask_words;
-  return pt;
-}
 
 SmallArgs small_args(const ladmm_batch *b) {
   const ladmm_case *c = b->c;
@@ -461,6 +447,7 @@ int destroy_batch_impl(ladmm_batch *b) {
   if (!b) return LADMM_OK;
   if (b->stream) hipStreamSynchronize(b->stream);
   for (auto &g : b->graph_cache) hipGraphExecDestroy(g.exec);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   for (hipEvent_t e : b->ev_pool) hipEventDestroy(e);
   for (void *p : b->allocs) hipFree(p);
   ctx_release(b->c->ctx, b->bytes);
@@ -946,11 +933,20 @@ int enqueue_iterations(ladmm_batch *b, int n) {
   for (const auto &g : b->graph_cache)
     if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2) exec = g.exec;
   if (!exec) {
-    HIPC(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    if (!b->cap_stream) HIPC(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    // the launches below go to the capture stream; the graph runs on b->stream
+    const hipStream_t run_stream = b->stream;
+    b->stream = b->cap_stream;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      b->stream = run_stream;
+      return fail(LADMM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
     int rc = LADMM_OK;
     for (int i = 0; i < n && rc == LADMM_OK; ++i) rc = iterate_any(b, i == n - 1);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    e = hipStreamEndCapture(b->stream, &graph);
+    b->stream = run_stream;
     if (rc == LADMM_OK && e != hipSuccess)
       rc = fail(LADMM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     if (rc == LADMM_OK) {

@@ -21,6 +21,7 @@
 // the reduction index contiguous; both are staged through LDS as rows with the
 // k index contiguous, so a lane's fragment is one 16-byte LDS read.
 #include "kernels.h"
+#include "warm.h"
 
 #include <math.h>
 
@@ -710,6 +711,32 @@ __global__ void k_w_from_q_bf(const float *__restrict__ q, int Np, int kp, Point
 hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
                        uint16_t *wh, uint16_t *wl) {
   hipLaunchKernelGGL(k_w_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, wh, wl);
+  return hipGetLastError();
+}
+
+// W' rows of warm-started plans as pairs, from their loaded q columns.
+__global__ void k_warm_w_bf(WarmCols w, const float *__restrict__ q, int Np, int kp,
+                            PointTable<float> pt, uint16_t *__restrict__ wh,
+                            uint16_t *__restrict__ wl) {
+  const int i = blockIdx.y;
+  if (i >= w.n) return;
+  const int j = w.col[i];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Np) return;
+  const float qv = q[(size_t)p * kp + j];
+  const float wv = 2.f * clip0u_f(qv, upper_bf(pt, pt.grp[p], p, j)) - qv;
+  uint16_t h, l;
+  split_pair((double)wv, h, l);
+  wh[(size_t)j * Np + p] = h;
+  wl[(size_t)j * Np + p] = l;
+}
+
+hipError_t warm_w_bf(hipStream_t s, const WarmCols &w, const float *q, uint16_t *wh, uint16_t *wl,
+                     int Np, int kp, const PointTable<float> &pt) {
+  if (w.n <= 0) return hipSuccess;
+  if (w.n > kWarmCols) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_warm_w_bf, dim3((unsigned)((Np + 255) / 256), (unsigned)w.n), dim3(256), 0, s,
+                     w, q, Np, kp, pt, wh, wl);
   return hipGetLastError();
 }
 

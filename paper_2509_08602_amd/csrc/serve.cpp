@@ -10,7 +10,8 @@
 //   2. admit queued plans, oldest request first, into free slots: the slot's
 //      columns of the iterates are zeroed and its table entries written (u, b,
 //      1/rho, LD mask), so the plan starts cold exactly as in a batch of its
-//      own;
+//      own; with a warm store, the columns are instead loaded from the stored
+//      solved plan of the nearest weighting;
 //   3. launch check_every iterations on every lane with work, each lane on its
 //      own stream so that lanes of different cases overlap on the device;
 //   4. wait for the lanes, apply each plan's stopping rule at the check, and
@@ -34,6 +35,7 @@
 #include <thread>
 
 #include "state.h"
+#include "warm.h"
 
 using namespace ladmm;
 using Clock = std::chrono::steady_clock;
@@ -75,6 +77,13 @@ struct Lane {
   bool dirty = false, any_reset = false, launched = false;
   Clock::time_point last_used;
   std::vector<int> ld_points;     // indices of the case's LD points
+  // warm-start store: final iterates of up to wcap converged plans
+  int wcap = 0, wcount = 0, wnext = 0;
+  void *wq = nullptr;             // wcap x Np (the iterate type)
+  double *wq2 = nullptr, *wqs = nullptr;   // wcap x mAp, wcap x n_sec
+  std::vector<ladmm_weights> ww;  // weighting of each entry
+  std::vector<double> wrho;       // final step size of each entry
+  std::vector<int> warm_src;      // per slot: entry to load at the next upload, -1 none
 
   int busy() const {
     int n = 0;
@@ -102,7 +111,9 @@ struct ladmm_server {
   double busy_ms = 0.0;
   std::vector<double> latency_ms;
   int32_t n_lanes = 0, busy_slots = 0;
+  int64_t warm_starts = 0;
   // worker-owned
+  int64_t warm_round = 0;   // warm starts of the current round
   std::vector<std::unique_ptr<Lane>> lanes;
   std::deque<Request *> pending;   // requests with plans not yet admitted
   std::vector<Request *> live;     // requests not yet final
@@ -157,7 +168,25 @@ void admit(Lane &L, int s, Request *r, int p) {
     set_u_column<double>(L, s, w, cnt);
   else
     set_u_column<float>(L, s, w, cnt);
-  const double rho = r->opts.rho0 * std::sqrt(r->opts.w0_bot / w.w_bot);
+  double rho = r->opts.rho0 * std::sqrt(r->opts.w0_bot / w.w_bot);
+  L.warm_src[s] = -1;
+  if (L.wcount > 0) {
+    // nearest stored weighting in slider coordinates
+    int best = -1;
+    double bd = 0.0;
+    for (int e = 0; e < L.wcount; ++e) {
+      const ladmm_weights &v = L.ww[e];
+      const double dt = v.w_t - w.w_t, dr = v.w_r - w.w_r, dl = v.w_ld - w.w_ld;
+      const double db = (std::log10(v.w_bot) - std::log10(w.w_bot)) / 3.0;
+      const double d = dt * dt + dr * dr + dl * dl + db * db;
+      if (best < 0 || d < bd) {
+        best = e;
+        bd = d;
+      }
+    }
+    L.warm_src[s] = best;
+    rho = L.wrho[best];
+  }
   L.h_invrho[s] = 1.0 / rho;
   L.h_wbot[s] = w.w_bot;
   for (int i = 0; i < c->n_iso; ++i) L.h_bbot[(size_t)i * kp + s] = c->hE[c->ntp + i] * w.w_bot;
@@ -206,6 +235,42 @@ int upload(Lane &L) {
     }
     HIPC(zero_columns<double>(s, b->qs, c->n_sec, kp, L.d_reset));
     HIPC(zero_columns<double>(s, b->q2, c->mAp, kp, L.d_reset));
+    // warm-started slots: columns from the store, then their W' columns
+    WarmCols wc{};
+    auto flush = [&]() -> int {
+      if (wc.n == 0) return LADMM_OK;
+      if (c->precision == LADMM_F64) {
+        HIPC(warm_load<double>(s, wc, (const double *)L.wq, L.wq2, L.wqs, c->Np, c->mAp, c->n_sec,
+                               kp, (double *)b->q, b->q2, b->qs));
+        HIPC(warm_w<double>(s, wc, (const double *)b->q, (double *)b->W, c->Np, kp,
+                            point_table<double>(b)));
+      } else {
+        HIPC(warm_load<float>(s, wc, (const float *)L.wq, L.wq2, L.wqs, c->Np, c->mAp, c->n_sec, kp,
+                              (float *)b->q, b->q2, b->qs));
+        if (c->precision == LADMM_F32) {
+          HIPC(warm_w<float>(s, wc, (const float *)b->q, (float *)b->W, c->Np, kp,
+                             point_table<float>(b)));
+        } else {
+          uint16_t *wh = (uint16_t *)b->W;
+          HIPC(warm_w_bf(s, wc, (const float *)b->q, wh, wh + (size_t)kp * c->Np, c->Np, kp,
+                         point_table<float>(b)));
+        }
+      }
+      wc.n = 0;
+      return LADMM_OK;
+    };
+    for (int j = 0; j < kp; ++j) {
+      if (L.warm_src[j] < 0) continue;
+      wc.col[wc.n] = j;
+      wc.ent[wc.n] = L.warm_src[j];
+      L.warm_src[j] = -1;
+      if (++wc.n == kWarmCols) {
+        int rc = flush();
+        if (rc) return rc;
+      }
+    }
+    int rc = flush();
+    if (rc) return rc;
   }
   L.dirty = false;
   return LADMM_OK;
@@ -262,6 +327,17 @@ int make_lane(ladmm_server *sv, ladmm_case *c, std::unique_ptr<Lane> *out) {
   if (rc == LADMM_OK) L->d_reset = (int32_t *)p;
   if (rc == LADMM_OK) rc = batch_alloc(b, &p, (size_t)kp * c->n_t * sizeof(double));
   if (rc == LADMM_OK) L->d_t = (double *)p;
+  L->warm_src.assign(kp, -1);
+  if (rc == LADMM_OK && sv->opts.warm_store > 0) {
+    L->wcap = sv->opts.warm_store;
+    rc = batch_alloc(b, &L->wq, (size_t)L->wcap * c->Np * Tsz);
+    if (rc == LADMM_OK) rc = batch_alloc(b, &p, (size_t)L->wcap * c->mAp * sizeof(double));
+    if (rc == LADMM_OK) L->wq2 = (double *)p;
+    if (rc == LADMM_OK) rc = batch_alloc(b, &p, (size_t)L->wcap * c->n_sec * sizeof(double));
+    if (rc == LADMM_OK) L->wqs = (double *)p;
+    L->ww.assign(L->wcap, ladmm_weights{});
+    L->wrho.assign(L->wcap, 0.0);
+  }
   if (rc == LADMM_OK) rc = prepare_batch(b);
   if (rc) {
     free_lane(L.get());
@@ -377,9 +453,36 @@ int retire(ladmm_server *sv, Lane &L, std::vector<Request *> *touched) {
   HIPC(hipMemcpyAsync(L.h_t, L.d_t, (size_t)b->kp * c->n_t * sizeof(double), hipMemcpyDeviceToHost,
                       b->stream));
   HIPC(hipStreamSynchronize(b->stream));
+  // converged plans enter the warm store (oldest entry replaced)
+  WarmCols wc{};
+  auto flush = [&]() -> int {
+    if (wc.n == 0) return LADMM_OK;
+    if (c->precision == LADMM_F64) {
+      HIPC(warm_save<double>(b->stream, wc, (const double *)b->q, b->q2, b->qs, c->Np, c->mAp,
+                             c->n_sec, b->kp, (double *)L.wq, L.wq2, L.wqs));
+    } else {
+      HIPC(warm_save<float>(b->stream, wc, (const float *)b->q, b->q2, b->qs, c->Np, c->mAp,
+                            c->n_sec, b->kp, (float *)L.wq, L.wq2, L.wqs));
+    }
+    wc.n = 0;
+    return LADMM_OK;
+  };
   for (int s = 0; s < b->kp; ++s) {
     Request *r = L.owner[s];
     if (!r || b->h_active[s]) continue;
+    if (L.wcap > 0 && b->status[s] == LADMM_PLAN_CONVERGED) {
+      const int e = L.wnext;
+      L.wnext = (L.wnext + 1) % L.wcap;
+      L.wcount = std::min(L.wcount + 1, L.wcap);
+      L.ww[e] = b->w[s];
+      L.wrho[e] = b->rho[s];
+      wc.col[wc.n] = s;
+      wc.ent[wc.n] = e;
+      if (++wc.n == kWarmCols) {
+        int rc = flush();
+        if (rc) return rc;
+      }
+    }
     const int p = L.plan[s];
     const double *t = L.h_t + (size_t)s * c->n_t;
     const double *f = &b->rec[(size_t)s * kFinal];
@@ -399,7 +502,7 @@ int retire(ladmm_server *sv, Lane &L, std::vector<Request *> *touched) {
     r->in_slots--;
     touched->push_back(r);
   }
-  return LADMM_OK;
+  return flush();
 }
 
 void worker_main(ladmm_server *sv) {
@@ -449,7 +552,10 @@ void worker_main(ladmm_server *sv) {
         continue;
       }
       for (int s = 0; s < L->b->kp && r->next < r->k; ++s)
-        if (!L->owner[s]) admit(*L, s, r, r->next);
+        if (!L->owner[s]) {
+          admit(*L, s, r, r->next);
+          sv->warm_round += L->warm_src[s] >= 0;
+        }
       if (r->next == r->k)
         sv->pending.erase(sv->pending.begin() + i);
       else
@@ -522,6 +628,8 @@ void worker_main(ladmm_server *sv) {
       std::lock_guard<std::mutex> lk(sv->mu);
       if (!run.empty()) sv->busy_ms += round_ms;
       sv->plan_iterations += pit;
+      sv->warm_starts += sv->warm_round;
+      sv->warm_round = 0;
       for (Request *r : touched) {
         r->done++;
         sv->plans_retired++;
@@ -593,8 +701,10 @@ extern "C" {
 
 int ladmm_server_create(ladmm_ctx *ctx, const ladmm_server_opts *opts, ladmm_server **out) {
   if (!ctx || !opts || !out) return fail(LADMM_E_INVALID, "server_create: null argument");
-  if (opts->slots < 1 || opts->slots > 4096 || opts->check_every < 1 || opts->max_lanes < 0)
-    return fail(LADMM_E_INVALID, "server_create: slots in [1, 4096], check_every >= 1, max_lanes >= 0");
+  if (opts->slots < 1 || opts->slots > 4096 || opts->check_every < 1 || opts->max_lanes < 0 ||
+      opts->warm_store < 0 || opts->warm_store > 65536)
+    return fail(LADMM_E_INVALID, "server_create: slots in [1, 4096], check_every >= 1, "
+                                 "max_lanes >= 0, warm_store in [0, 65536]");
   ladmm_server *sv = new ladmm_server();
   sv->ctx = ctx;
   sv->opts = *opts;
@@ -711,6 +821,16 @@ int ladmm_cancel(ladmm_server *sv, uint64_t ticket) {
   return LADMM_OK;
 }
 
+int ladmm_server_reset_stats(ladmm_server *sv) {
+  if (!sv) return fail(LADMM_E_INVALID, "server_reset_stats: null argument");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->submitted = sv->completed = sv->cancelled = sv->failed = sv->plans_retired = 0;
+  sv->plan_iterations = sv->warm_starts = 0;
+  sv->busy_ms = 0.0;
+  sv->latency_ms.clear();
+  return LADMM_OK;
+}
+
 int ladmm_server_get_stats(ladmm_server *sv, ladmm_server_stats *out) {
   if (!sv || !out) return fail(LADMM_E_INVALID, "server_get_stats: null argument");
   std::lock_guard<std::mutex> lk(sv->mu);
@@ -721,6 +841,7 @@ int ladmm_server_get_stats(ladmm_server *sv, ladmm_server_stats *out) {
   s.failed = sv->failed;
   s.plans_completed = sv->plans_retired;
   s.plan_iterations = sv->plan_iterations;
+  s.warm_starts = sv->warm_starts;
   s.busy_ms = sv->busy_ms;
   s.lanes = sv->n_lanes;
   s.busy_slots = sv->busy_slots;

@@ -134,6 +134,9 @@ struct ladmm_batch {
   struct Graph { int n, cfg1, cfg2; hipGraphExec_t exec; };
   bool graphs = true;
   std::vector<Graph> graph_cache;
+  // captures run on a stream of their own that does not synchronize with the
+  // legacy stream, so other threads' synchronous copies never meet a capture
+  hipStream_t cap_stream = nullptr;
   // per-kernel event timing
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -159,6 +162,21 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
                       bool slots = false);
 int destroy_batch_impl(ladmm_batch *b);
 SmallArgs small_args(const ladmm_batch *b);
+// Point tables of a batch (group, sign, bounds, LD mask) for the kernels.
+template <typename T>
+PointTable<T> point_table(const ladmm_batch *b) {
+  const ladmm_case *c = b->c;
+  PointTable<T> pt;
+  pt.grp = c->grp;
+  pt.sig = (const T *)c->sig;
+  pt.is_ld = c->is_ld;
+  pt.is_oar = c->is_oar;
+  pt.utab = (const T *)b->utab;
+  pt.ldu = b->kp;
+  pt.mask = b->mask;
+  pt.mask_words = b->mask_words;
+  return pt;
+}
 // Tile configurations of the two dose-matrix products (autotuned or default).
 int prepare_batch(ladmm_batch *b);
 // Enqueue n iterations (the last with statistics) and the read-back of the

@@ -75,13 +75,14 @@ class _Result(C.Structure):
 
 class _ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("check_every", C.c_int32), ("max_lanes", C.c_int32),
-                ("autotune", C.c_int32), ("eager", C.c_int32)]
+                ("autotune", C.c_int32), ("eager", C.c_int32), ("warm_store", C.c_int32)]
 
 
 class _ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
                 ("failed", C.c_int64), ("plans_completed", C.c_int64),
-                ("plan_iterations", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("plan_iterations", C.c_int64), ("warm_starts", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double),
                 ("max_ms", C.c_double), ("mean_ms", C.c_double), ("busy_ms", C.c_double),
                 ("lanes", C.c_int32), ("busy_slots", C.c_int32)]
 
@@ -150,6 +151,7 @@ _SIGS = {
     "ladmm_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int64]),
     "ladmm_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "ladmm_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(_ServerStats)]),
+    "ladmm_server_reset_stats": (C.c_int, [C.c_void_p]),
     "ladmm_last_error": (C.c_char_p, []),
     "ladmm_version": (C.c_char_p, []),
 }
@@ -559,13 +561,13 @@ class Server:
     """Continuous-batching server (ladmm_server_*): requests of k plans on resident cases."""
 
     def __init__(self, ctx: Context, slots: int = 96, check_every: int = 50, max_lanes: int = 0,
-                 autotune: bool = True, eager: bool = False):
+                 autotune: bool = True, eager: bool = False, warm_store: int = 0):
         self.ctx = ctx
         self.check_every = int(check_every)
         self._h = C.c_void_p()
         self._live = {}
         o = _ServerOpts(int(slots), int(check_every), int(max_lanes), 1 if autotune else 0,
-                        1 if eager else 0)
+                        1 if eager else 0, int(warm_store))
         _check(library().ladmm_server_create(ctx._h, C.byref(o), C.byref(self._h)))
         _SERVERS.add(self)
 
@@ -581,6 +583,9 @@ class Server:
         s = _ServerStats()
         _check(library().ladmm_server_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in _ServerStats._fields_}
+
+    def reset_stats(self):
+        _check(library().ladmm_server_reset_stats(self._h))
 
     def close(self):
         if self._h:

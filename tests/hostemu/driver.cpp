@@ -213,6 +213,43 @@ int main(int argc, char **argv) {
       save(dir + "/alone_i" + tag + ".i32", ri[q].data(), ri[q].size());
     }
     (void)off;
+    // Warm starts: the last 6 plans twice on a server with a store.  Loose
+    // tolerances let every plan converge at its first check and enter the
+    // store; the second request starts from it (nearest weighting = itself), so
+    // its K iterations continue the first request's: the result is that of 2K
+    // iterations from cold (same step sizes; the balancing is off here).
+    {
+      ladmm_server_opts wopt{32, K, 0, 0, 0, 16};
+      ladmm_server *ws = nullptr;
+      CHECK(ladmm_server_create(ctx, &wopt, &ws));
+      ladmm_opts ow = ro;
+      ow.max_iter = 1000; ow.tol_gap = 1e30; ow.tol_pri = 1e30; ow.tol_dual = 1e30;
+      std::vector<double> f1(kB), f2(kB), t2((size_t)kB * n_t), f3(kB), t3((size_t)kB * n_t);
+      std::vector<int32_t> i1(kB), i2(kB), s1(kB), s2(kB), i3(kB), s3(kB);
+      ladmm_result r1{nullptr, nullptr, f1.data(), nullptr, nullptr, nullptr, nullptr, i1.data(), s1.data()};
+      ladmm_result r2{t2.data(), nullptr, f2.data(), nullptr, nullptr, nullptr, nullptr, i2.data(), s2.data()};
+      ladmm_result r3{t3.data(), nullptr, f3.data(), nullptr, nullptr, nullptr, nullptr, i3.data(), s3.data()};
+      uint64_t t1 = 0, tw = 0;
+      CHECK(ladmm_submit(ws, cs, kB, &w[kA], mb, &ow, &r1, &t1));
+      CHECK(ladmm_wait(ws, t1, -1));
+      CHECK(ladmm_submit(ws, cs, kB, &w[kA], mb, &ow, &r2, &tw));
+      CHECK(ladmm_wait(ws, tw, -1));
+      ladmm_server_stats wst{};
+      CHECK(ladmm_server_get_stats(ws, &wst));
+      if (wst.warm_starts != kB) {
+        fprintf(stderr, "warm starts %lld\n", (long long)wst.warm_starts);
+        return 4;
+      }
+      CHECK(ladmm_server_destroy(ws));
+      ladmm_opts o2 = ro;
+      o2.max_iter = 2 * K; o2.check_every = K;
+      CHECK(ladmm_solve_batch(cs, kB, &w[kA], mb, &o2, &r3));
+      save(dir + "/warm_t.f64", t2.data(), t2.size());
+      save(dir + "/warm_f.f64", f2.data(), f2.size());
+      save(dir + "/warm_i.i32", i2.data(), i2.size());
+      save(dir + "/cold2_t.f64", t3.data(), t3.size());
+      save(dir + "/cold2_f.f64", f3.data(), f3.size());
+    }
   }
   CHECK(ladmm_destroy_case(cs));
   CHECK(ladmm_ctx_destroy(ctx));

@@ -172,6 +172,8 @@ hipError_t hipMemcpy(void *, const void *, size_t, hipMemcpyKind);
 hipError_t hipMemcpyAsync(void *, const void *, size_t, hipMemcpyKind, hipStream_t);
 hipError_t hipMemsetAsync(void *, int, size_t, hipStream_t);
 hipError_t hipStreamCreate(hipStream_t *);
+#define hipStreamNonBlocking 0x01
+hipError_t hipStreamCreateWithFlags(hipStream_t *, unsigned);
 hipError_t hipStreamDestroy(hipStream_t);
 hipError_t hipStreamSynchronize(hipStream_t);
 hipError_t hipEventCreate(hipEvent_t *);

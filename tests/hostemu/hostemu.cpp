@@ -138,6 +138,7 @@ hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
   return hipSuccess;
 }
 hipError_t hipStreamCreate(hipStream_t *s) { *s = (hipStream_t)0x1; return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t)0x2; return hipSuccess; }
 hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
 hipError_t hipStreamSynchronize(hipStream_t) { return hostemu::g_capture ? hipErrorInvalidValue : hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t *e) { *e = new hostemu_event(); return hipSuccess; }

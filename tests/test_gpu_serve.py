@@ -177,3 +177,51 @@ def test_hbm_budget_evicts_idle_lanes(ctx, mini, c0):
     same(res[0], ladmm.solve_batch(ca, w[:3], opts=o))
     same(res[1], ladmm.solve_batch(cb, w[3:], opts=o))
     same(res[2], ladmm.solve_batch(ca, w[3:], opts=o))
+
+
+@pytest.mark.parametrize("precision", ["f64", "bf16x3"])
+def test_warm_start_from_nearest_solved_plan(ctx, c0, precision):
+    """A server with a warm store starts each admitted plan from the stored
+    solved plan of the nearest weighting.  The 9 slider plans solved a second
+    time start from their own solutions and stop after far fewer iterations
+    with the same objective; perturbed weightings converge in fewer iterations than
+    cold and agree with the plans solved alone within their stopping
+    tolerance (each stops at a 1e-3 gap)."""
+    say("serve warm start c0", precision)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    w0 = cases.config_weights(0)
+    # the library's default step-size rule (balanced from rho0 = 1e4): every plan converges
+    o = ladmm.Options(max_iter=20000, check_every=50, tol_gap=1e-3, tol_pri=1e-3, tol_dual=1e-3,
+                      rho0=1e4, w0_bot=cases.W0_BOT, autotune=False, adapt_rho=True)
+    srv = ladmm.Server(ctx, slots=32, check_every=50, autotune=False, warm_store=64)
+    first = srv.submit(dc, w0, opts=o).result()
+    say("  first pass status", first["plan_status"].tolist(), "iterations", first["iters"].tolist())
+    assert np.all(first["plan_status"] == ladmm.PLAN_CONVERGED)   # all enter the store
+    second = srv.submit(dc, w0, opts=o).result()
+    assert srv.stats()["warm_starts"] == w0.shape[0]
+    assert np.all(second["plan_status"] == ladmm.PLAN_CONVERGED)
+    # the stopping criteria are not monotone along the ADMM iterates, so a plan
+    # restarted from its own stopping point need not pass at its very next
+    # check; it never needs more iterations than from cold, and far fewer in
+    # total (the exact continuation is checked in the host emulation)
+    say("  second pass iterations", second["iters"].tolist())
+    assert np.all(second["iters"] <= first["iters"]), (second["iters"], first["iters"])
+    assert second["iters"].sum() < 0.5 * first["iters"].sum()
+    rel0 = np.abs(second["objective"] - first["objective"]) / np.abs(first["objective"])
+    assert rel0.max() <= 2e-3, rel0
+    # perturbed sliders: w_LD + 0.05 and the BOT slider + 0.05 (w_BOT x 10^0.15)
+    w1 = w0.copy()
+    w1[:, 2] = np.clip(w1[:, 2] + 0.05, 0.0, 1.0)
+    w1[:, 3] *= 10 ** 0.15
+    alone = ladmm.solve_batch(dc, w1, opts=o)
+    warm = srv.submit(dc, w1, opts=o).result()
+    st = srv.stats()
+    srv.close()
+    say("  cold iterations", first["iters"].tolist(), "perturbed alone", alone["iters"].tolist(),
+        "perturbed warm", warm["iters"].tolist(), "warm starts", st["warm_starts"])
+    assert st["warm_starts"] == 2 * w0.shape[0]
+    assert np.all(warm["plan_status"] == ladmm.PLAN_CONVERGED)
+    assert warm["iters"].sum() < alone["iters"].sum()
+    # both stop at a 1e-3 gap, each within 1e-3 of the plan's optimum
+    rel = np.abs(warm["objective"] - alone["objective"]) / np.abs(alone["objective"])
+    assert rel.max() <= 2e-3, rel

@@ -249,3 +249,10 @@ def test_emulated_serving(driver, tmp_path):
         assert np.array_equal(it, np.fromfile(os.path.join(d, f"alone_i{tag}.i32"), np.int32))
         F = olp.planning_objective(case, w[sl], t.T, mask[sl])[0]
         assert rel_err(f, F) < 1e-5
+    # warm starts: 2 iterations from the stored state of the same plans after 2
+    # iterations equal 4 iterations from cold (up to the rounding of the
+    # rebuilt W' columns)
+    kk = 6
+    assert np.fromfile(os.path.join(d, "warm_i.i32"), np.int32).tolist() == [2] * kk
+    assert rel_err(rd(d, "warm_f.f64", (kk,)), rd(d, "cold2_f.f64", (kk,))) < 1e-6
+    assert rel_err(rd(d, "warm_t.f64", (kk, n_t)), rd(d, "cold2_t.f64", (kk, n_t))) < 1e-5
