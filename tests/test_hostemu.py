@@ -97,12 +97,6 @@ def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, 
         np.ascontiguousarray(vox, np.float64).tofile(os.path.join(d, "vox.f64"))
 
 
-def run(driver, d):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
-    res = subprocess.run([driver, d], capture_output=True, text=True, env=env, timeout=900)
-    assert res.returncode == 0, (res.stdout + res.stderr)[-6000:]
-
-
 def rd(d, name, shape, dtype=np.float64):
     return np.fromfile(os.path.join(d, name), dtype).reshape(shape)
 
@@ -117,21 +111,109 @@ def small_case(seed=0, oar=False):
     return cases.build_case(spec, seed)
 
 
-@pytest.mark.parametrize("precision,tol,tiles,solve,k", [("f64", 1e-11, (0, 0), 0, 5),
-                                                         ("f32", 2e-3, (-1, -1), 12, 5),
-                                                         ("bf16x3", 2e-4, (-1, -1), 0, 5),
-                                                         ("bf16x3", 2e-4, (4, 4), 0, 70)])
-def test_emulated_iterations_match_oracle(driver, tmp_path, precision, tol, tiles, solve, k):
+# Every emulated run is prepared and started at once (the runs are independent
+# single-threaded processes), then each test checks its own run's outputs.
+ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
+              ("f32", 2e-3, (-1, -1), 12, 5),
+              ("bf16x3", 2e-4, (-1, -1), 0, 5),
+              ("bf16x3", 2e-4, (4, 4), 0, 70)]
+
+
+def _iter_name(precision, tiles, k):
+    return f"iter-{precision}-{tiles[0]}{tiles[1]}-{k}"
+
+
+def _iter_spec(k):
+    return small_case(1), cases.random_weights(k, 2)
+
+
+def _mask_spec():
+    case = small_case(3, oar=True)
+    w = cases.random_weights(4, 5)
+    types = case.point_types()
+    rng = np.random.default_rng(1)
+    mask = np.zeros((4, case.n_points), bool)
+    ld = np.nonzero(types == cases.LD)[0]
+    for j in range(4):
+        mask[j, ld[rng.random(ld.size) < 0.6]] = True
+    vols = cases.random_volumes(6, 700, 4)
+    n_ld = np.array([50, 0, 120, 33, 500, 80])
+    vox = case.kernel.dose_rate(case.ld_candidates[:333])
+    return dict(case=case, w=w, mask=mask, vols=vols, n_ld=n_ld, vox=vox)
+
+
+def _tp_spec():
+    case = small_case(5)
+    w = cases.random_weights(2, 8)
+    cand = case.ld_candidates[::7][:200]
+    return dict(case=case, w=w, cand=cand, vox=case.kernel.dose_rate(cand))
+
+
+def _serve_spec():
+    case = small_case(7)
+    k = 36
+    w = cases.random_weights(k, 9)
+    types = case.point_types()
+    rng = np.random.default_rng(4)
+    mask = np.zeros((k, case.n_points), bool)
+    ld = np.nonzero(types == cases.LD)[0]
+    for j in range(k):
+        mask[j, ld[rng.random(ld.size) < 0.5]] = True
+    return dict(case=case, w=w, mask=mask)
+
+
+def _prepare(root):
+    runs = {}
+    for precision, _, tiles, solve, k in ITER_CASES:
+        d = os.path.join(root, _iter_name(precision, tiles, k))
+        case, w = _iter_spec(k)
+        write_inputs(d, case, w, precision, 4, solve_iters=solve, tiles=tiles)
+        runs[_iter_name(precision, tiles, k)] = d
+    m = _mask_spec()
+    d = os.path.join(root, "mask")
+    write_inputs(d, m["case"], m["w"], "f64", 3, mask=m["mask"], vols=m["vols"], n_ld=m["n_ld"],
+                 seed=77, vox=m["vox"], d_ld=0.05, delta=0.1, tiles=(2, 1))
+    runs["mask"] = d
+    t = _tp_spec()
+    d = os.path.join(root, "tp")
+    write_inputs(d, t["case"], t["w"], "f64", 2, seed=41, vox=t["vox"], d_ld=0.05, delta=0.1,
+                 tiles=(1, 3), two_pass=True)
+    runs["tp"] = d
+    v = _serve_spec()
+    d = os.path.join(root, "serve")
+    write_inputs(d, v["case"], v["w"], "f32", 1, mask=v["mask"], tiles=(0, 0), serve=True)
+    runs["serve"] = d
+    return runs
+
+
+@pytest.fixture(scope="module")
+def emu(driver, tmp_path_factory):
+    runs = _prepare(str(tmp_path_factory.mktemp("emu")))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+
+    def go(d):
+        return subprocess.run([driver, d], capture_output=True, text=True, env=env, timeout=900)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(len(runs), os.cpu_count() or 4))) as ex:
+        futs = {name: ex.submit(go, d) for name, d in runs.items()}
+        return {name: (runs[name], f.result()) for name, f in futs.items()}
+
+
+def finished(emu, name):
+    d, res = emu[name]
+    assert res.returncode == 0, (res.stdout + res.stderr)[-6000:]
+    return d
+
+
+@pytest.mark.parametrize("precision,tol,tiles,solve,k", ITER_CASES)
+def test_emulated_iterations_match_oracle(emu, precision, tol, tiles, solve, k):
     """tiles (-1, -1): the autotuner launches every tile configuration; (4, 4)
     at 70 plans (96 columns): the direct-A BF16-pair kernels of both products.  The
     BF16-pair products carry about 2^-16 relative error per product, of the
     order of the FP32 path's, hence the same kind of tolerance."""
-    case = small_case(1)
-    w = cases.random_weights(k, 2)
-    d = str(tmp_path / precision)
+    d = finished(emu, _iter_name(precision, tiles, k))
+    case, w = _iter_spec(k)
     iters = 4
-    write_inputs(d, case, w, precision, iters, solve_iters=solve, tiles=tiles)
-    run(driver, d)
     lp = olp.assemble(case, w)
     slp = olp.precondition(lp, olp.bot_scale(case))
     m, n = slp.A.shape
@@ -154,22 +236,10 @@ def test_emulated_iterations_match_oracle(driver, tmp_path, precision, tol, tile
     assert rel_err(res[0], F) < (1e-10 if precision == "f64" else 1e-5 if precision == "f32" else 2e-4)
 
 
-def test_emulated_ld_mask_oar_band_and_alg1(driver, tmp_path):
-    case = small_case(3, oar=True)
-    w = cases.random_weights(4, 5)
-    types = case.point_types()
-    rng = np.random.default_rng(1)
-    mask = np.zeros((4, case.n_points), bool)
-    ld = np.nonzero(types == cases.LD)[0]
-    for j in range(4):
-        mask[j, ld[rng.random(ld.size) < 0.6]] = True
-    vols = cases.random_volumes(6, 700, 4)
-    n_ld = np.array([50, 0, 120, 33, 500, 80])
-    vox = case.kernel.dose_rate(case.ld_candidates[:333])
-    d = str(tmp_path / "mask")
-    write_inputs(d, case, w, "f64", 3, mask=mask, vols=vols, n_ld=n_ld, seed=77, vox=vox,
-                 d_ld=0.05, delta=0.1, tiles=(2, 1))
-    run(driver, d)
+def test_emulated_ld_mask_oar_band_and_alg1(emu):
+    d = finished(emu, "mask")
+    m = _mask_spec()
+    case, w, mask, vols, n_ld, vox = m["case"], m["w"], m["mask"], m["vols"], m["n_ld"], m["vox"]
     lp = olp.assemble(case, w, mask)
     slp = olp.precondition(lp, olp.bot_scale(case))
     rho = olp.rho_rule(w[:, 3], 1000.0, cases.W0_BOT)
@@ -190,18 +260,13 @@ def test_emulated_ld_mask_oar_band_and_alg1(driver, tmp_path):
     assert np.array_equal(band, ref)
 
 
-def test_emulated_two_pass(driver, tmp_path):
+def test_emulated_two_pass(emu):
     """Both passes through ladmm_two_pass: the pass-2 point set equals the oracle's
     band + Algorithm 1 from the pass-1 shot times, and the pass-2 objective is the
     oracle's F of the returned shot times on the rebuilt case."""
-    case = small_case(5)
-    w = cases.random_weights(2, 8)
-    cand = case.ld_candidates[::7][:200]
-    vox = case.kernel.dose_rate(cand)
-    d = str(tmp_path / "tp")
-    write_inputs(d, case, w, "f64", 2, seed=41, vox=vox, d_ld=0.05, delta=0.1, tiles=(1, 3),
-                 two_pass=True)
-    run(driver, d)
+    d = finished(emu, "tp")
+    t = _tp_spec()
+    case, w, cand, vox = t["case"], t["w"], t["cand"], t["vox"]
     k, n_t = w.shape[0], case.n_t
     t1 = rd(d, "tp_t1.f64", (k, n_t))
     vols = odose.ld_band(odose.dose(vox, t1.T), 0.05, 0.1)
@@ -219,24 +284,16 @@ def test_emulated_two_pass(driver, tmp_path):
     assert rel_err(rd(d, "tp_f2.f64", (k,)), F2) < 1e-10
 
 
-def test_emulated_serving(driver, tmp_path):
+def test_emulated_serving(emu):
     """Continuous batching through ladmm_submit/wait/cancel: a cancelled request,
     then two requests whose plans share 32 slots (later plans start in slots
     freed by earlier ones).  Every plan's shot times, objective and iteration
     count equal those of ladmm_solve_batch on its own request, bitwise, and the
     objective is the oracle's F of the returned shot times."""
-    case = small_case(7)
-    k = 36
-    w = cases.random_weights(k, 9)
-    types = case.point_types()
-    rng = np.random.default_rng(4)
-    mask = np.zeros((k, case.n_points), bool)
-    ld = np.nonzero(types == cases.LD)[0]
-    for j in range(k):
-        mask[j, ld[rng.random(ld.size) < 0.5]] = True
-    d = str(tmp_path / "serve")
-    write_inputs(d, case, w, "f32", 1, mask=mask, tiles=(0, 0), serve=True)
-    run(driver, d)
+    d = finished(emu, "serve")
+    v = _serve_spec()
+    case, w, mask = v["case"], v["w"], v["mask"]
+    k = w.shape[0]
     n_t = case.n_t
     for tag, sl, iters in (("A", slice(0, k - 6), 4), ("B", slice(k - 6, k), 2)):
         kk = sl.stop - sl.start
