@@ -299,6 +299,24 @@ int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
                    ladmm_result *pass1_out, ladmm_result *out, int64_t *P, int64_t *n_points2,
                    double *times_ms);
 
+/* The same with several low-dose groups replaced at once (App. A: two low-dose
+ * thresholds D_1,LD and D_2,LD, each with its own volume [D_i,LD, D_i,LD +
+ * Delta), in both passes).  Set i gives the threshold, candidates, counts and
+ * seed of the group sets[i].ld_group (distinct groups); its band and its
+ * Algorithm 1 selection are computed from the same pass-1 dose, and the pass-2
+ * case appends the selected points of every set, in set order, each in its own
+ * group, with plan j's bound restricted to its own subsets.
+ *   P:         optional host output, capacity sum of n_vox: the selected voxel
+ *              indices of every set, concatenated in set order (each set's
+ *              indices refer to its own candidates).
+ *   n_points2: optional host output[n_sets + 1]: |P_i| per set, then the pass-2
+ *              point count.
+ * ladmm_two_pass is this call with one set. */
+int ladmm_two_pass_sets(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
+                        const ladmm_weights *w, const ladmm_opts *opts, int32_t n_sets,
+                        const ladmm_pass2_desc *sets, ladmm_result *pass1_out, ladmm_result *out,
+                        int64_t *P, int64_t *n_points2, double *times_ms);
+
 /* ---- Serving: continuous batching of plan requests ---------------------------
  *
  * Plans of one case are independent columns that share the dose block and the

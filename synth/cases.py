@@ -136,22 +136,28 @@ class Case:
     def point_types(self):
         return np.array([g.type for g in self.groups], dtype=np.int32)[self.group]
 
-    def with_points(self, keep: np.ndarray, extra_ld=None, ld_group=None, name=None):
+    def with_points(self, keep: np.ndarray, extra_ld=None, ld_group=None, name=None, extra=None):
         """A copy that keeps rows `keep` and appends low-dose points `extra_ld`.
 
         `extra_ld` are voxel coordinates; their dose rows are evaluated from the
-        same kernel model, and they join group `ld_group`.  Used to build the
-        second-pass case once its low-dose point set is known.
+        same kernel model, and they join group `ld_group`.  `extra` is a list of
+        such (coordinates, group) pairs appended in order after `extra_ld`.
+        Used to build the second-pass case once its low-dose point sets are
+        known.
         """
         keep = np.asarray(keep)
         dose = self.dose[keep]
         group = self.group[keep]
         coords = self.coords[keep]
-        if extra_ld is not None and len(extra_ld):
-            extra_ld = np.asarray(extra_ld, dtype=np.int32)
-            dose = np.concatenate([dose, self.kernel.dose_rate(extra_ld, dtype=self.dose.dtype)])
-            group = np.concatenate([group, np.full(len(extra_ld), ld_group, np.int32)])
-            coords = np.concatenate([coords, extra_ld])
+        parts = [] if extra_ld is None else [(extra_ld, ld_group)]
+        parts += list(extra or [])
+        for pts, g in parts:
+            if pts is None or not len(pts):
+                continue
+            pts = np.asarray(pts, dtype=np.int32)
+            dose = np.concatenate([dose, self.kernel.dose_rate(pts, dtype=self.dose.dtype)])
+            group = np.concatenate([group, np.full(len(pts), g, np.int32)])
+            coords = np.concatenate([coords, pts])
         return dataclasses.replace(self, dose=np.ascontiguousarray(dose), group=group,
                                    coords=coords, name=name or self.name + "+pass2")
 
@@ -222,6 +228,8 @@ def build_case(spec: dict, seed: int, dtype=np.float64) -> Case:
       ld_region   : ("cube", edge_mm) around the grid centre, or ("shell", r_out_mm)
                     beyond the ring
       ld_fraction : D_LD / D_T,mean
+      ld_levels   : optional list of D_LD / D_T,mean, one low-dose group per level
+                    (App. A uses two thresholds); n_ld points are drawn for each
       n_iso       : isocentres (split over targets by volume^(2/3))
       oars        : list of (center_zyx, radii_zyx, max_dose_Gy, n_points)
       sectors, collimators, fwhm, output_factor, phi_cal, offset_frac
@@ -281,7 +289,9 @@ def build_case(spec: dict, seed: int, dtype=np.float64) -> Case:
         ld_cand = outside & (dist <= ring_mm + region[1])
     ld_cand_vox = np.argwhere(ld_cand).astype(np.int32)
     n_ld = int(spec["n_ld"])
-    ld_vox = ld_cand_vox[np.sort(rng.choice(len(ld_cand_vox), n_ld, replace=False))]
+    levels = list(spec.get("ld_levels", [spec.get("ld_fraction", 0.5)]))
+    ld_sets = [ld_cand_vox[np.sort(rng.choice(len(ld_cand_vox), n_ld, replace=False))]
+               for _ in levels]
 
     # groups and points, in the block order of App. A: TS_k, TI_k, R_k, LD, O_m
     groups, coords, gid = [], [], []
@@ -297,9 +307,9 @@ def build_case(spec: dict, seed: int, dtype=np.float64) -> Case:
     for k in range(n_tg):
         groups.append(Group(RING, k, float(presc[k]), 1.0 / n_tg))
         coords.append(ring_vox[ring_owner == k]); gid.append(len(groups) - 1)
-    d_ld = float(spec.get("ld_fraction", 0.5)) * d_mean
-    groups.append(Group(LD, 0, d_ld, 1.0))
-    coords.append(ld_vox); gid.append(len(groups) - 1)
+    for lvl, (frac, ld_vox) in enumerate(zip(levels, ld_sets)):
+        groups.append(Group(LD, lvl, float(frac) * d_mean, 1.0))
+        coords.append(ld_vox); gid.append(len(groups) - 1)
     for m, (c, r, dmax, npts) in enumerate(spec.get("oars", [])):
         om = _surface(_ellipsoid_mask(shape, c, r))
         ov = np.argwhere(om)

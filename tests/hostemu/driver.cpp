@@ -131,26 +131,38 @@ int main(int argc, char **argv) {
   }
   if (band_vox > 0 && run_two_pass) {
     // both passes, a few fixed iterations each
+    // one second-pass set per low-dose group: threshold d_ld / (i + 1), seed + 1 + i
     auto vox = load<double>(dir + "/vox.f64", (size_t)band_vox * n_t);
-    int ld_group = -1;
+    std::vector<int> ldg;
     for (int g = 0; g < G; ++g)
-      if (groups[g].type == LADMM_PT_LD) ld_group = g;
+      if (groups[g].type == LADMM_PT_LD) ldg.push_back(g);
+    const int ns = (int)ldg.size();
     std::vector<int32_t> nld(k, 25);
-    ladmm_pass2_desc p2{band_vox, vox.data(), d_ld, delta, nld.data(), seed + 1, ld_group};
+    std::vector<ladmm_pass2_desc> sets(ns);
+    for (int i = 0; i < ns; ++i)
+      sets[i] = ladmm_pass2_desc{band_vox, vox.data(), d_ld / (i + 1), delta, nld.data(),
+                                 seed + 1 + (uint64_t)i, ldg[i]};
     ladmm_opts to = o;
     to.max_iter = 6; to.check_every = 3; to.tol_gap = 0.0; to.autotune = 0;
     std::vector<double> t1((size_t)k * n_t), t2((size_t)k * n_t), f2(k);
     std::vector<int32_t> it1(k), st1(k), it2(k), st2(k);
     ladmm_result r1{t1.data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, it1.data(), st1.data()};
     ladmm_result r2{t2.data(), nullptr, f2.data(), nullptr, nullptr, nullptr, nullptr, it2.data(), st2.data()};
-    std::vector<int64_t> P(band_vox);
-    int64_t n2[2] = {0, 0};
+    std::vector<int64_t> P((size_t)band_vox * ns);
+    std::vector<int64_t> n2(ns + 1, 0);
     double times[5];
-    CHECK(ladmm_two_pass(ctx, &d, k, w.data(), &to, &p2, &r1, &r2, P.data(), n2, times));
+    if (ns == 1)
+      CHECK(ladmm_two_pass(ctx, &d, k, w.data(), &to, &sets[0], &r1, &r2, P.data(), n2.data(), times));
+    else
+      CHECK(ladmm_two_pass_sets(ctx, &d, k, w.data(), &to, ns, sets.data(), &r1, &r2, P.data(),
+                                n2.data(), times));
+    int64_t total = 0;
+    for (int i = 0; i < ns; ++i) total += n2[i];
     save(dir + "/tp_t1.f64", t1.data(), t1.size());
     save(dir + "/tp_t2.f64", t2.data(), t2.size());
     save(dir + "/tp_f2.f64", f2.data(), f2.size());
-    save(dir + "/tp_P.i64", P.data(), (size_t)n2[0]);
+    save(dir + "/tp_P.i64", P.data(), (size_t)total);
+    save(dir + "/tp_n.i64", n2.data(), n2.size());
   }
   if (serve) {
     // Continuous batching on 32 slots: a long request cancelled at once, then

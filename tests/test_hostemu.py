@@ -142,8 +142,12 @@ def _mask_spec():
     return dict(case=case, w=w, mask=mask, vols=vols, n_ld=n_ld, vox=vox)
 
 
-def _tp_spec():
-    case = small_case(5)
+def _tp_spec(levels=None):
+    if levels is None:
+        case = small_case(5)
+    else:
+        spec = cases.mini_spec(n_iso=2, sectors=8, collimators=3, radius=3.0, n_ring=90, n_ld=60)
+        case = cases.build_case(dict(spec, ld_levels=levels), 5)
     w = cases.random_weights(2, 8)
     cand = case.ld_candidates[::7][:200]
     return dict(case=case, w=w, cand=cand, vox=case.kernel.dose_rate(cand))
@@ -179,6 +183,11 @@ def _prepare(root):
     write_inputs(d, t["case"], t["w"], "f64", 2, seed=41, vox=t["vox"], d_ld=0.05, delta=0.1,
                  tiles=(1, 3), two_pass=True)
     runs["tp"] = d
+    t = _tp_spec([0.5, 0.3])
+    d = os.path.join(root, "tp2")
+    write_inputs(d, t["case"], t["w"], "f64", 2, seed=41, vox=t["vox"], d_ld=0.05, delta=0.1,
+                 tiles=(1, 3), two_pass=True)
+    runs["tp2"] = d
     v = _serve_spec()
     d = os.path.join(root, "serve")
     write_inputs(d, v["case"], v["w"], "f32", 1, mask=v["mask"], tiles=(0, 0), serve=True)
@@ -260,25 +269,35 @@ def test_emulated_ld_mask_oar_band_and_alg1(emu):
     assert np.array_equal(band, ref)
 
 
-def test_emulated_two_pass(emu):
-    """Both passes through ladmm_two_pass: the pass-2 point set equals the oracle's
-    band + Algorithm 1 from the pass-1 shot times, and the pass-2 objective is the
-    oracle's F of the returned shot times on the rebuilt case."""
-    d = finished(emu, "tp")
-    t = _tp_spec()
+@pytest.mark.parametrize("run,levels", [("tp", None), ("tp2", [0.5, 0.3])])
+def test_emulated_two_pass(emu, run, levels):
+    """Both passes through ladmm_two_pass (one low-dose group) and
+    ladmm_two_pass_sets (two low-dose groups with thresholds d and d / 2, App.
+    A): every set's pass-2 point set equals the oracle's band + Algorithm 1 from
+    the pass-1 shot times, and the pass-2 objective is the oracle's F of the
+    returned shot times on the rebuilt case."""
+    d = finished(emu, run)
+    t = _tp_spec(levels)
     case, w, cand, vox = t["case"], t["w"], t["cand"], t["vox"]
     k, n_t = w.shape[0], case.n_t
+    ld_groups = [g for g, grp in enumerate(case.groups) if grp.type == cases.LD]
+    counts = np.fromfile(os.path.join(d, "tp_n.i64"), np.int64)
+    assert len(counts) == len(ld_groups) + 1
+    P_all = np.fromfile(os.path.join(d, "tp_P.i64"), np.int64)
     t1 = rd(d, "tp_t1.f64", (k, n_t))
-    vols = odose.ld_band(odose.dose(vox, t1.T), 0.05, 0.1)
-    Pref, pref = oalg1.select_ld_points(vols, np.full(k, 25), 42)
-    P = np.fromfile(os.path.join(d, "tp_P.i64"), np.int64)
-    assert P.tolist() == Pref
-    ld_group = [g.type for g in case.groups].index(cases.LD)
-    keep = np.nonzero(case.group != ld_group)[0]
-    case2 = case.with_points(keep, extra_ld=cand[np.array(Pref, dtype=np.int64)], ld_group=ld_group)
-    mask2 = np.zeros((k, case2.n_points), bool)
-    if len(Pref):
-        mask2[:, len(keep):] = oalg1.masks_over(Pref, pref)
+    dose1 = odose.dose(vox, t1.T)
+    keep = np.nonzero(~np.isin(case.group, ld_groups))[0]
+    extra, blocks, at = [], [], 0
+    for i, g in enumerate(ld_groups):
+        vols = odose.ld_band(dose1, 0.05 / (i + 1), 0.1)
+        Pref, pref = oalg1.select_ld_points(vols, np.full(k, 25), 42 + i)
+        assert P_all[at:at + counts[i]].tolist() == Pref, i
+        at += int(counts[i])
+        extra.append((cand[np.array(Pref, dtype=np.int64)], g))
+        blocks.append(oalg1.masks_over(Pref, pref) if len(Pref) else np.zeros((k, 0), bool))
+    case2 = case.with_points(keep, extra=extra)
+    assert case2.n_points == counts[-1]
+    mask2 = np.concatenate([np.zeros((k, len(keep)), bool)] + blocks, axis=1)
     t2 = rd(d, "tp_t2.f64", (k, n_t))
     F2 = olp.planning_objective(case2, w, t2.T, mask2)[0]
     assert rel_err(rd(d, "tp_f2.f64", (k,)), F2) < 1e-10
