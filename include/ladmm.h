@@ -245,6 +245,29 @@ int ladmm_solve_batch(ladmm_case *c, int32_t k, const ladmm_weights *w,
 int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double d_ld,
                         double delta, uint64_t *vol_bits);
 
+/* Clinical metrics of the batch's plans from their current shot times, on a
+ * dose grid (Sec. 2.A; used to compare plans in Sec. 3.B), with the dose
+ * d_j(v) = phi_vox(v) t_j computed on the device in FP64:
+ *   coverage       = |{v in T : d_j(v) >= D(v)}| / |T|, T the target voxels and
+ *                    D(v) the prescription of v's target;
+ *   selectivity    = |{v in T : d_j(v) >= D(v)}| / |{v : d_j(v) >= d_ref}|;
+ *   gradient index = |{v : d_j(v) >= d_ref / 2}| / |{v : d_j(v) >= d_ref}|;
+ *   beam-on time   = sum over isocentres of max over sectors of the summed shot
+ *                    times of the sector (in the time unit of the dose rates:
+ *                    minutes for Gy/min).
+ * With one target (or equal prescriptions) d_ref is the prescription and these
+ * are the paper's definitions; with unequal prescriptions the paper defines no
+ * global gradient index.
+ *   phi_vox:    host, n_vox x n_t dose rates of the grid voxels, >= 0.
+ *   vox_target: host, n_vox target indices in [0, n_targets), -1 outside.
+ *   presc:      host, n_targets prescription doses > 0.
+ *   out:        host, k x 4 (coverage, selectivity, gradient index, beam-on
+ *               time); NaN where a denominator is zero.
+ * Allocates its scratch for the call. */
+int ladmm_batch_metrics(ladmm_batch *b, int64_t n_vox, const double *phi_vox,
+                        const int32_t *vox_target, int32_t n_targets, const double *presc,
+                        double d_ref, double *out);
+
 /* Algorithm 1 (overlapping low-dose point sampling, Sec. 2.C.2), integer exact.
  * Plans are taken in order of decreasing density w_j = min(1, N_LD,j / |V_j|)
  * (ties: lower index first); a plan with |V_j| = 0 or N_LD,j <= 0 gets no

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -25,6 +26,7 @@
 #include <vector>
 
 #include "state.h"
+#include "metrics.h"
 
 namespace ladmm {
 
@@ -1396,48 +1398,148 @@ int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_i
   return LADMM_OK;
 }
 
-int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double d_ld,
-                        double delta, uint64_t *vol_bits) {
-  if (!b) return fail(LADMM_E_STATE, "null batch");
-  if (n_vox < 1 || !phi_vox || !vol_bits || !(delta > 0) || !std::isfinite(d_ld))
-    return fail(LADMM_E_INVALID, "ld_band: bad arguments");
-  if (n_vox > (int64_t)1 << 30) return fail(LADMM_E_INVALID, "ld_band: too many voxels");
+}  // extern "C"
+
+namespace {
+
+// FP64 dose of every plan of batch b at n_vox voxels, from its current shot
+// times: *dd (n_vox rows padded to the tile, kp columns) and, if dt_host is not
+// NULL, the shot times themselves (ntp x kp) on the host.  The caller frees *dd.
+int grid_dose(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double **dd,
+              std::vector<double> *dt_host, const char *who) {
+  if (n_vox < 1 || !phi_vox) return fail(LADMM_E_INVALID, std::string(who) + ": bad arguments");
+  if (n_vox > (int64_t)1 << 30) return fail(LADMM_E_INVALID, std::string(who) + ": too many voxels");
   ladmm_case *c = b->c;
   HIPC(hipSetDevice(c->ctx->device));
-  const int nv = (int)n_vox, nvp = round_up(nv, kTileRows), W = (nv + 63) / 64;
+  const int nv = (int)n_vox, nvp = round_up(nv, kTileRows);
   const size_t nd = (size_t)nv * c->n_t;
   for (size_t e = 0; e < nd; ++e)
     if (!(phi_vox[e] >= 0.0) || !std::isfinite(phi_vox[e]))
-      return fail(LADMM_E_INVALID, "ld_band: dose rates must be finite and >= 0");
+      return fail(LADMM_E_INVALID, std::string(who) + ": dose rates must be finite and >= 0");
   std::vector<double> hp((size_t)nvp * c->ntp, 0.0);
   for (int v = 0; v < nv; ++v)
     std::memcpy(&hp[(size_t)v * c->ntp], phi_vox + (size_t)v * c->n_t, c->n_t * sizeof(double));
-  double *dphi = nullptr, *dt = nullptr, *dd = nullptr;
-  uint64_t *dbits = nullptr;
+  double *dphi = nullptr, *dt = nullptr;
+  *dd = nullptr;
   hipError_t e = hipMalloc((void **)&dphi, hp.size() * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void **)&dt, (size_t)c->ntp * b->kp * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void **)&dd, (size_t)nvp * b->kp * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void **)&dbits, (size_t)b->k * W * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void **)dd, (size_t)nvp * b->kp * sizeof(double));
   if (e == hipSuccess)
     e = hipMemcpyAsync(dphi, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, b->stream);
   SmallArgs sa = small_args(b);
   if (e == hipSuccess) e = shot_times_matrix(b->stream, sa, b->q2, dt);
   if (e == hipSuccess) {
     EpiArgs<double> ea{};
-    ea.C = dd;
+    ea.C = *dd;
     ea.ldc = b->kp;
     e = gemm_nn<double>(b->stream, EPI_STORE, dphi, c->ntp, dt, b->kp, nvp, b->kp, c->ntp, ea);
   }
+  if (e == hipSuccess && dt_host) {
+    dt_host->assign((size_t)c->ntp * b->kp, 0.0);
+    e = hipMemcpyAsync(dt_host->data(), dt, dt_host->size() * sizeof(double), hipMemcpyDeviceToHost,
+                       b->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (dphi) hipFree(dphi);
+  if (dt) hipFree(dt);
+  if (e != hipSuccess) {
+    if (*dd) hipFree(*dd);
+    *dd = nullptr;
+    return fail(LADMM_E_DEVICE, std::string(who) + ": " + hipGetErrorString(e));
+  }
+  return LADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ladmm_batch_ld_band(ladmm_batch *b, int64_t n_vox, const double *phi_vox, double d_ld,
+                        double delta, uint64_t *vol_bits) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (!vol_bits || !(delta > 0) || !std::isfinite(d_ld))
+    return fail(LADMM_E_INVALID, "ld_band: bad arguments");
+  double *dd = nullptr;
+  int rc = grid_dose(b, n_vox, phi_vox, &dd, nullptr, "ld_band");
+  if (rc) return rc;
+  const int nv = (int)n_vox, W = (nv + 63) / 64;
+  uint64_t *dbits = nullptr;
+  hipError_t e = hipMalloc((void **)&dbits, (size_t)b->k * W * sizeof(uint64_t));
   if (e == hipSuccess) e = band_bits(b->stream, dd, b->kp, nv, b->k, d_ld, d_ld + delta, dbits);
   if (e == hipSuccess)
     e = hipMemcpyAsync(vol_bits, dbits, (size_t)b->k * W * sizeof(uint64_t), hipMemcpyDeviceToHost,
                        b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-  if (dphi) hipFree(dphi);
-  if (dt) hipFree(dt);
-  if (dd) hipFree(dd);
+  hipFree(dd);
   if (dbits) hipFree(dbits);
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("ld_band: ") + hipGetErrorString(e));
+  return LADMM_OK;
+}
+
+int ladmm_batch_metrics(ladmm_batch *b, int64_t n_vox, const double *phi_vox,
+                        const int32_t *vox_target, int32_t n_targets, const double *presc,
+                        double d_ref, double *out) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (!vox_target || !presc || !out || n_targets < 1 || !(d_ref > 0) || !std::isfinite(d_ref))
+    return fail(LADMM_E_INVALID, "metrics: bad arguments");
+  int64_t n_target_vox = 0;
+  for (int64_t v = 0; v < n_vox; ++v) {
+    if (vox_target[v] < -1 || vox_target[v] >= n_targets)
+      return fail(LADMM_E_INVALID, "metrics: voxel target index out of range");
+    n_target_vox += vox_target[v] >= 0;
+  }
+  for (int i = 0; i < n_targets; ++i)
+    if (!(presc[i] > 0) || !std::isfinite(presc[i]))
+      return fail(LADMM_E_INVALID, "metrics: prescriptions must be > 0");
+  ladmm_case *c = b->c;
+  double *dd = nullptr;
+  std::vector<double> t;
+  int rc = grid_dose(b, n_vox, phi_vox, &dd, &t, "metrics");
+  if (rc) return rc;
+  const int nv = (int)n_vox, k = b->k;
+  int32_t *dtgt = nullptr;
+  double *dpresc = nullptr;
+  unsigned long long *dcnt = nullptr;
+  std::vector<unsigned long long> cnt((size_t)3 * k, 0);
+  hipError_t e = hipMalloc((void **)&dtgt, (size_t)nv * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void **)&dpresc, (size_t)n_targets * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&dcnt, cnt.size() * sizeof(unsigned long long));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtgt, vox_target, (size_t)nv * sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dpresc, presc, (size_t)n_targets * sizeof(double), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dcnt, cnt.data(), cnt.size() * sizeof(unsigned long long),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = plan_metric_counts(b->stream, dd, b->kp, nv, k, dtgt, dpresc, d_ref, dcnt);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cnt.data(), dcnt, cnt.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  hipFree(dd);
+  if (dtgt) hipFree(dtgt);
+  if (dpresc) hipFree(dpresc);
+  if (dcnt) hipFree(dcnt);
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("metrics: ") + hipGetErrorString(e));
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int j = 0; j < k; ++j) {
+    const double cov = (double)cnt[3 * j], piv = (double)cnt[3 * j + 1], piv2 = (double)cnt[3 * j + 2];
+    double bot = 0.0;
+    for (int i = 0; i < c->n_iso; ++i) {
+      double best = 0.0;
+      for (int s = 0; s < c->S; ++s) {
+        double sec = 0.0;
+        for (int cc = 0; cc < c->C; ++cc) sec += t[(size_t)((i * c->S + s) * c->C + cc) * b->kp + j];
+        best = std::max(best, sec);
+      }
+      bot += best;
+    }
+    out[4 * j + 0] = n_target_vox > 0 ? cov / (double)n_target_vox : nan;
+    out[4 * j + 1] = piv > 0 ? cov / piv : nan;
+    out[4 * j + 2] = piv > 0 ? piv2 / piv : nan;
+    out[4 * j + 3] = bot;
+  }
   return LADMM_OK;
 }
 

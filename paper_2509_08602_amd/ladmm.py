@@ -127,6 +127,8 @@ _SIGS = {
     "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ladmm_batch_metrics": (C.c_int, [C.c_void_p, C.c_int64, _DP, _IP, C.c_int32, _DP, C.c_double,
+                                      _DP]),
     "ladmm_batch_set_profiling": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_tiles": (C.c_int, [C.c_void_p, _IP, _IP]),
     "ladmm_batch_set_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -388,6 +390,17 @@ class Batch:
 
     def set_tiles(self, gemm1, gemm2):
         _check(library().ladmm_batch_set_tiles(self._h, int(gemm1), int(gemm2)))
+
+    def metrics(self, phi_vox, vox_target, presc, d_ref):
+        """Clinical metrics (k x 4: coverage, selectivity, gradient index, beam-on
+        time) of the current shot times on a dose grid (ladmm_batch_metrics)."""
+        phi = np.ascontiguousarray(phi_vox, np.float64)
+        tgt = np.ascontiguousarray(vox_target, np.int32)
+        pr = np.ascontiguousarray(np.atleast_1d(presc), np.float64)
+        out = np.empty((self.k, 4))
+        _check(library().ladmm_batch_metrics(self._h, phi.shape[0], _dptr(phi), tgt.ctypes.data_as(_IP),
+                                             pr.size, _dptr(pr), float(d_ref), _dptr(out)))
+        return out
 
     def set_graphs(self, on=True):
         """Replay captured HIP graphs of each run chunk (default) or launch one by one."""
