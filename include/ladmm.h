@@ -340,6 +340,21 @@ int ladmm_two_pass_sets(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
                         const ladmm_pass2_desc *sets, ladmm_result *pass1_out, ladmm_result *out,
                         int64_t *P, int64_t *n_points2, double *times_ms);
 
+/* More than two passes (Sec. 2.C repeated): pass p + 1 takes its low-dose
+ * points from the dose of pass p by the same band and Algorithm 1 steps (each
+ * set with its own threshold and seed), on the points of pass 1 outside the
+ * replaced groups; every pass starts from zero iterates.
+ *   n_passes:  >= 2 (2 is ladmm_two_pass_sets), at most 64.
+ *   pass_out:  optional array of n_passes result records (entry p: pass p + 1;
+ *              NULL pointers inside a record are skipped).
+ *   P, n_points: as for ladmm_two_pass_sets, for the last pass.
+ *   times_ms:  optional host output[2 + 3 (n_passes - 1)]: pass-1 setup and
+ *              solve, then per later pass band + Algorithm 1, setup, solve. */
+int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k, const ladmm_weights *w,
+                 const ladmm_opts *opts, int32_t n_sets, const ladmm_pass2_desc *sets,
+                 int32_t n_passes, ladmm_result *pass_out, int64_t *P, int64_t *n_points,
+                 double *times_ms);
+
 /* ---- Serving: continuous batching of plan requests ---------------------------
  *
  * Plans of one case are independent columns that share the dose block and the

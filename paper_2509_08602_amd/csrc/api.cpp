@@ -1598,125 +1598,149 @@ int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint6
   return LADMM_OK;
 }
 
-int ladmm_two_pass_sets(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k,
-                        const ladmm_weights *w, const ladmm_opts *opts, int32_t n_sets,
-                        const ladmm_pass2_desc *sets, ladmm_result *pass1_out, ladmm_result *out,
-                        int64_t *P_out, int64_t *n_points2, double *times_ms) {
-  if (!ctx || !d1 || !w || !opts || !sets || !out) return fail(LADMM_E_INVALID, "two_pass: null argument");
-  if (k < 1 || n_sets < 1) return fail(LADMM_E_INVALID, "two_pass: k >= 1 and n_sets >= 1");
+int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const ladmm_weights *w,
+                 const ladmm_opts *opts, int32_t n_sets, const ladmm_pass2_desc *sets,
+                 int32_t n_passes, ladmm_result *pass_out, int64_t *P_out, int64_t *n_points,
+                 double *times_ms) {
+  if (!ctx || !d1 || !w || !opts || !sets) return fail(LADMM_E_INVALID, "passes: null argument");
+  if (k < 1 || n_sets < 1 || n_passes < 2 || n_passes > 64)
+    return fail(LADMM_E_INVALID, "passes: k >= 1, n_sets >= 1, n_passes in [2, 64]");
   for (int i = 0; i < n_sets; ++i) {
     const ladmm_pass2_desc &p2 = sets[i];
     if (p2.n_vox < 1 || !p2.phi_vox || !p2.n_ld)
-      return fail(LADMM_E_INVALID, "two_pass: bad second-pass description");
+      return fail(LADMM_E_INVALID, "passes: bad second-pass description");
     if (p2.ld_group < 0 || p2.ld_group >= d1->n_groups || d1->groups[p2.ld_group].type != LADMM_PT_LD)
-      return fail(LADMM_E_INVALID, "two_pass: ld_group must name a low-dose group");
+      return fail(LADMM_E_INVALID, "passes: ld_group must name a low-dose group");
     for (int j = 0; j < i; ++j)
       if (sets[j].ld_group == p2.ld_group)
-        return fail(LADMM_E_INVALID, "two_pass: each set replaces a different low-dose group");
+        return fail(LADMM_E_INVALID, "passes: each set replaces a different low-dose group");
   }
   using clk = std::chrono::steady_clock;
   auto ms = [](clk::time_point a, clk::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
   };
-  double tm[5] = {0, 0, 0, 0, 0};
+  std::vector<double> tm;
   const int n_t = d1->n_iso * d1->n_sectors * d1->n_collimators;
-  // pass 1
-  auto t0 = clk::now();
-  ladmm_case *c1 = nullptr;
-  int rc = ladmm_create_case(ctx, d1, &c1);
-  if (rc) return rc;
-  auto t1 = clk::now();
-  ladmm_batch *b1 = nullptr;
-  rc = ladmm_batch_create(c1, k, w, nullptr, nullptr, opts, &b1);
-  if (rc == LADMM_OK) rc = ladmm_batch_run(b1);
-  if (rc == LADMM_OK && pass1_out) rc = ladmm_batch_results(b1, pass1_out);
-  auto t2 = clk::now();
-  // per set: low-dose band of the pass-1 dose at its threshold, then Algorithm 1
-  std::vector<std::vector<int64_t>> P(n_sets);
-  std::vector<std::vector<uint64_t>> masks(n_sets);
-  std::vector<int64_t> nP(n_sets, 0);
-  for (int i = 0; i < n_sets && rc == LADMM_OK; ++i) {
-    const ladmm_pass2_desc &p2 = sets[i];
-    const int64_t nv = p2.n_vox;
-    const size_t Wv = (size_t)((nv + 63) / 64);
-    std::vector<uint64_t> vol((size_t)k * Wv);
-    masks[i].assign((size_t)k * Wv, 0);
-    P[i].assign(nv, 0);
-    rc = ladmm_batch_ld_band(b1, nv, p2.phi_vox, p2.d_ld, p2.delta, vol.data());
-    if (rc == LADMM_OK)
-      rc = ladmm_select_ld_points(ctx, k, nv, vol.data(), p2.n_ld, p2.seed, P[i].data(), &nP[i],
-                                  masks[i].data());
-  }
-  if (b1) ladmm_batch_destroy(b1);
-  ladmm_destroy_case(c1);
-  if (rc) return rc;
-  auto t3 = clk::now();
-  // pass-2 case: every point of pass 1 outside the replaced groups, then the
-  // points of each set's P in its low-dose group
+  // points kept in every later pass: those outside the replaced groups
   std::vector<int32_t> keep;
   for (int p = 0; p < d1->n_points; ++p) {
     bool replaced = false;
     for (int i = 0; i < n_sets; ++i) replaced |= d1->point_group[p] == sets[i].ld_group;
     if (!replaced) keep.push_back(p);
   }
-  int64_t N2 = (int64_t)keep.size();
-  for (int i = 0; i < n_sets; ++i) N2 += nP[i];
-  if (N2 < 1 || N2 > INT32_MAX) return fail(LADMM_E_INVALID, "two_pass: empty or too large pass 2");
-  std::vector<double> dose2((size_t)N2 * n_t);
-  std::vector<int32_t> grp2(N2);
-  for (size_t i = 0; i < keep.size(); ++i) {
-    std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
-    grp2[i] = d1->point_group[keep[i]];
-  }
-  const int W2 = (int)((N2 + 63) / 64);
-  std::vector<uint64_t> mask2((size_t)k * W2, 0);
-  int64_t at = (int64_t)keep.size();
-  for (int s = 0; s < n_sets; ++s) {
-    const ladmm_pass2_desc &p2 = sets[s];
-    const size_t Wv = (size_t)((p2.n_vox + 63) / 64);
-    for (int64_t i = 0; i < nP[s]; ++i) {
-      std::memcpy(&dose2[(size_t)(at + i) * n_t], p2.phi_vox + (size_t)P[s][i] * n_t,
-                  n_t * sizeof(double));
-      grp2[at + i] = p2.ld_group;
+  // pass 1
+  auto t0 = clk::now();
+  ladmm_case *cur_c = nullptr;
+  ladmm_batch *cur_b = nullptr;
+  int rc = ladmm_create_case(ctx, d1, &cur_c);
+  if (rc) return rc;
+  auto t1 = clk::now();
+  rc = ladmm_batch_create(cur_c, k, w, nullptr, nullptr, opts, &cur_b);
+  if (rc == LADMM_OK) rc = ladmm_batch_run(cur_b);
+  if (rc == LADMM_OK && pass_out) rc = ladmm_batch_results(cur_b, &pass_out[0]);
+  auto t2 = clk::now();
+  tm.push_back(ms(t0, t1));
+  tm.push_back(ms(t1, t2));
+  std::vector<std::vector<int64_t>> P(n_sets);
+  std::vector<int64_t> nP(n_sets, 0);
+  int64_t N2 = 0;
+  for (int pass = 1; pass < n_passes && rc == LADMM_OK; ++pass) {
+    // per set: low-dose band of the previous pass's dose at its threshold, then Algorithm 1
+    auto ta = clk::now();
+    std::vector<std::vector<uint64_t>> masks(n_sets);
+    for (int i = 0; i < n_sets && rc == LADMM_OK; ++i) {
+      const ladmm_pass2_desc &p2 = sets[i];
+      const int64_t nv = p2.n_vox;
+      const size_t Wv = (size_t)((nv + 63) / 64);
+      std::vector<uint64_t> vol((size_t)k * Wv);
+      masks[i].assign((size_t)k * Wv, 0);
+      P[i].assign(nv, 0);
+      rc = ladmm_batch_ld_band(cur_b, nv, p2.phi_vox, p2.d_ld, p2.delta, vol.data());
+      if (rc == LADMM_OK)
+        rc = ladmm_select_ld_points(ctx, k, nv, vol.data(), p2.n_ld, p2.seed, P[i].data(), &nP[i],
+                                    masks[i].data());
     }
-    for (int j = 0; j < k; ++j)
-      for (int64_t i = 0; i < nP[s]; ++i)
-        if ((masks[s][(size_t)j * Wv + (i >> 6)] >> (i & 63)) & 1ull) {
-          const int64_t pt = at + i;
-          mask2[(size_t)j * W2 + (pt >> 6)] |= 1ull << (pt & 63);
-        }
-    at += nP[s];
+    ladmm_batch_destroy(cur_b);
+    ladmm_destroy_case(cur_c);
+    cur_b = nullptr;
+    cur_c = nullptr;
+    if (rc) break;
+    auto tb = clk::now();
+    // this pass's case: the kept points, then the points of each set's P in its group
+    N2 = (int64_t)keep.size();
+    for (int i = 0; i < n_sets; ++i) N2 += nP[i];
+    if (N2 < 1 || N2 > INT32_MAX) {
+      rc = fail(LADMM_E_INVALID, "passes: empty or too large pass");
+      break;
+    }
+    std::vector<double> dose2((size_t)N2 * n_t);
+    std::vector<int32_t> grp2(N2);
+    for (size_t i = 0; i < keep.size(); ++i) {
+      std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
+      grp2[i] = d1->point_group[keep[i]];
+    }
+    const int W2 = (int)((N2 + 63) / 64);
+    std::vector<uint64_t> mask2((size_t)k * W2, 0);
+    int64_t at = (int64_t)keep.size();
+    for (int st = 0; st < n_sets; ++st) {
+      const ladmm_pass2_desc &p2 = sets[st];
+      const size_t Wv = (size_t)((p2.n_vox + 63) / 64);
+      for (int64_t i = 0; i < nP[st]; ++i) {
+        std::memcpy(&dose2[(size_t)(at + i) * n_t], p2.phi_vox + (size_t)P[st][i] * n_t,
+                    n_t * sizeof(double));
+        grp2[at + i] = p2.ld_group;
+      }
+      for (int j = 0; j < k; ++j)
+        for (int64_t i = 0; i < nP[st]; ++i)
+          if ((masks[st][(size_t)j * Wv + (i >> 6)] >> (i & 63)) & 1ull) {
+            const int64_t pt = at + i;
+            mask2[(size_t)j * W2 + (pt >> 6)] |= 1ull << (pt & 63);
+          }
+      at += nP[st];
+    }
+    ladmm_case_desc d2 = *d1;
+    d2.n_points = (int32_t)N2;
+    d2.dose = dose2.data();
+    d2.point_group = grp2.data();
+    rc = ladmm_create_case(ctx, &d2, &cur_c);
+    if (rc) break;
+    auto tc = clk::now();
+    rc = ladmm_batch_create(cur_c, k, w, mask2.data(), nullptr, opts, &cur_b);
+    if (rc == LADMM_OK) rc = ladmm_batch_run(cur_b);
+    if (rc == LADMM_OK && pass_out) rc = ladmm_batch_results(cur_b, &pass_out[pass]);
+    auto td = clk::now();
+    tm.push_back(ms(ta, tb));
+    tm.push_back(ms(tb, tc));
+    tm.push_back(ms(tc, td));
   }
-  ladmm_case_desc d2 = *d1;
-  d2.n_points = (int32_t)N2;
-  d2.dose = dose2.data();
-  d2.point_group = grp2.data();
-  ladmm_case *c2 = nullptr;
-  rc = ladmm_create_case(ctx, &d2, &c2);
+  if (cur_b) ladmm_batch_destroy(cur_b);
+  if (cur_c) ladmm_destroy_case(cur_c);
   if (rc) return rc;
-  auto t4 = clk::now();
-  ladmm_batch *b2 = nullptr;
-  rc = ladmm_batch_create(c2, k, w, mask2.data(), nullptr, opts, &b2);
-  if (rc == LADMM_OK) rc = ladmm_batch_run(b2);
-  if (rc == LADMM_OK) rc = ladmm_batch_results(b2, out);
-  auto t5 = clk::now();
-  if (b2) ladmm_batch_destroy(b2);
-  ladmm_destroy_case(c2);
-  if (rc) return rc;
-  tm[0] = ms(t0, t1); tm[1] = ms(t1, t2); tm[2] = ms(t2, t3); tm[3] = ms(t3, t4); tm[4] = ms(t4, t5);
-  if (times_ms) std::memcpy(times_ms, tm, sizeof(tm));
+  if (times_ms) std::memcpy(times_ms, tm.data(), tm.size() * sizeof(double));
   if (P_out) {
     int64_t o = 0;
-    for (int s = 0; s < n_sets; ++s) {
-      std::memcpy(P_out + o, P[s].data(), (size_t)nP[s] * sizeof(int64_t));
-      o += nP[s];
+    for (int st = 0; st < n_sets; ++st) {
+      std::memcpy(P_out + o, P[st].data(), (size_t)nP[st] * sizeof(int64_t));
+      o += nP[st];
     }
   }
-  if (n_points2) {
-    for (int s = 0; s < n_sets; ++s) n_points2[s] = nP[s];
-    n_points2[n_sets] = N2;
+  if (n_points) {
+    for (int st = 0; st < n_sets; ++st) n_points[st] = nP[st];
+    n_points[n_sets] = N2;
   }
   return LADMM_OK;
+}
+
+int ladmm_two_pass_sets(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k,
+                        const ladmm_weights *w, const ladmm_opts *opts, int32_t n_sets,
+                        const ladmm_pass2_desc *sets, ladmm_result *pass1_out, ladmm_result *out,
+                        int64_t *P_out, int64_t *n_points2, double *times_ms) {
+  if (!out) return fail(LADMM_E_INVALID, "two_pass: null argument");
+  ladmm_result res[2];
+  std::memset(&res[0], 0, sizeof(res[0]));
+  if (pass1_out) res[0] = *pass1_out;
+  res[1] = *out;
+  return ladmm_passes(ctx, d1, k, w, opts, n_sets, sets, 2, res, P_out, n_points2, times_ms);
 }
 
 int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const ladmm_weights *w,

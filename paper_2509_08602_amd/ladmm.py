@@ -148,6 +148,10 @@ _SIGS = {
                                  C.POINTER(_Opts), C.c_int32, C.POINTER(_Pass2), C.c_void_p,
                                  C.POINTER(_Result), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  _DP]),
+    "ladmm_passes": (C.c_int, [C.c_void_p, C.POINTER(_CaseDesc), C.c_int32, C.POINTER(_Weights),
+                               C.POINTER(_Opts), C.c_int32, C.POINTER(_Pass2), C.c_int32,
+                               C.POINTER(_Result), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                               _DP]),
     "ladmm_server_create": (C.c_int, [C.c_void_p, C.POINTER(_ServerOpts), C.POINTER(C.c_void_p)]),
     "ladmm_server_destroy": (C.c_int, [C.c_void_p]),
     "ladmm_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(_Weights),
@@ -511,6 +515,44 @@ def two_pass_sets(ctx: Context, case, weights, sets, precision="f64", opts: Opti
         parts.append(P[at:at + n2[i]].copy())
         at += int(n2[i])
     return out1, out2, parts, int(n2[-1]), times
+
+
+def passes(ctx: Context, case, weights, sets, n_passes, precision="f64", opts: Options | None = None):
+    """ladmm_passes: n_passes passes, each later one taking its low-dose points
+    from the previous pass's dose (sets as for two_pass_sets).
+
+    Returns ([results of every pass], [P_i of the last pass per set], last pass's
+    point count, times_ms)."""
+    groups = [(g.type, g.structure, g.threshold, g.share) for g in case.groups]
+    desc, keep = _case_desc(case.dose, case.group, groups, case.n_iso, case.n_sectors,
+                            case.n_collimators, case.prescription_mean, case.phi_cal, precision)
+    w, k = _weights(weights)
+    hold, descs = [], (_Pass2 * len(sets))()
+    for i, st in enumerate(sets):
+        phi = np.ascontiguousarray(st["phi_vox"], np.float64)
+        nld = np.ascontiguousarray(np.broadcast_to(np.asarray(st["n_ld"], np.int32), (k,)))
+        hold += [phi, nld]
+        descs[i] = _Pass2(phi.shape[0], _dptr(phi), float(st["d_ld"]), float(st["delta"]),
+                          nld.ctypes.data_as(_IP), C.c_uint64(int(st["seed"]) & ((1 << 64) - 1)),
+                          int(st["ld_group"]))
+    n_t = case.dose.shape[1]
+    outs, recs = [], (_Result * n_passes)()
+    for q in range(n_passes):
+        o_q, r_q = _result_buffers(k, n_t, case.n_iso)
+        outs.append(o_q)
+        recs[q] = r_q
+    P = np.zeros(sum(int(d.n_vox) for d in descs), np.int64)
+    n2 = np.zeros(len(sets) + 1, np.int64)
+    times = np.zeros(2 + 3 * (n_passes - 1))
+    o = (opts or Options()).c()
+    _check(library().ladmm_passes(ctx._h, C.byref(desc), k, w, C.byref(o), len(sets), descs,
+                                  int(n_passes), recs, P.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  n2.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(times)))
+    parts, at = [], 0
+    for i in range(len(sets)):
+        parts.append(P[at:at + n2[i]].copy())
+        at += int(n2[i])
+    return outs, parts, int(n2[-1]), times
 
 
 def solve_batch(case: Case, weights, ld_mask=None, opts: Options | None = None):

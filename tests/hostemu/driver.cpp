@@ -150,12 +150,30 @@ int main(int argc, char **argv) {
     ladmm_result r2{t2.data(), nullptr, f2.data(), nullptr, nullptr, nullptr, nullptr, it2.data(), st2.data()};
     std::vector<int64_t> P((size_t)band_vox * ns);
     std::vector<int64_t> n2(ns + 1, 0);
-    double times[5];
-    if (ns == 1)
-      CHECK(ladmm_two_pass(ctx, &d, k, w.data(), &to, &sets[0], &r1, &r2, P.data(), n2.data(), times));
-    else
+    const int n_passes = run_two_pass == 1 ? 2 : run_two_pass;
+    std::vector<double> times(2 + 3 * (n_passes - 1));
+    std::vector<std::vector<double>> tmid(n_passes);
+    if (n_passes > 2) {
+      // every pass's shot times (the middle ones let the test redo each selection)
+      std::vector<ladmm_result> rs(n_passes);
+      for (int q = 0; q < n_passes; ++q) {
+        tmid[q].resize((size_t)k * n_t);
+        rs[q] = ladmm_result{tmid[q].data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr};
+      }
+      rs[0] = r1;
+      rs[n_passes - 1] = r2;
+      CHECK(ladmm_passes(ctx, &d, k, w.data(), &to, ns, sets.data(), n_passes, rs.data(), P.data(),
+                         n2.data(), times.data()));
+      for (int q = 1; q + 1 < n_passes; ++q)
+        save(dir + "/tp_tmid" + std::to_string(q + 1) + ".f64", tmid[q].data(), tmid[q].size());
+    } else if (ns == 1) {
+      CHECK(ladmm_two_pass(ctx, &d, k, w.data(), &to, &sets[0], &r1, &r2, P.data(), n2.data(),
+                           times.data()));
+    } else {
       CHECK(ladmm_two_pass_sets(ctx, &d, k, w.data(), &to, ns, sets.data(), &r1, &r2, P.data(),
-                                n2.data(), times));
+                                n2.data(), times.data()));
+    }
     int64_t total = 0;
     for (int i = 0; i < ns; ++i) total += n2[i];
     save(dir + "/tp_t1.f64", t1.data(), t1.size());

@@ -108,3 +108,39 @@ def test_two_pass_two_low_dose_thresholds_c0():
     say("pass-2 rel err", rel, "status", r2["plan_status"], "iters", r2["iters"])
     # every plan, also the two the 20,000-iteration budget stops (measured 1.5e-4)
     assert np.all(rel < 1e-3), rel
+
+
+def test_three_passes_c0():
+    """A third pass (Sec. 2.C repeated): its low-dose points are the oracle's band
+    + Algorithm 1 of the second pass's dose, bit for bit, and every plan of the
+    third pass reaches the exact optimum of its LP within 1e-3."""
+    say("three passes c0 f64")
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    k = w.shape[0]
+    ld_group = [g.type for g in case.groups].index(cases.LD)
+    cand = case.ld_candidates
+    phi = case.kernel.dose_rate(cand)
+    D = case.prescription_mean
+    st = dict(phi_vox=phi, d_ld=0.5 * D, delta=0.1 * D, n_ld=500, seed=12345, ld_group=ld_group)
+    opts = ladmm.Options(max_iter=60000, check_every=50, tol_gap=1e-5, tol_pri=1e-5,
+                         tol_dual=1e-5, rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False)
+    ctx = ladmm.Context(0)
+    outs, Ps, n3, times = ladmm.passes(ctx, case, w, [st], 3, "f64", opts)
+    say("times ms", times, "|P|", len(Ps[0]), "N3", n3)
+    vols = odose.ld_band(odose.dose(phi, outs[1]["t"].T), st["d_ld"], st["delta"])
+    Pref, pref = oalg1.select_ld_points(vols, np.full(k, st["n_ld"]), st["seed"])
+    assert Ps[0].tolist() == Pref
+    keep = np.nonzero(case.group != ld_group)[0]
+    case3 = case.with_points(keep, extra_ld=cand[np.array(Pref)], ld_group=ld_group)
+    assert case3.n_points == n3
+    mask3 = np.zeros((k, n3), bool)
+    mask3[:, len(keep):] = oalg1.masks_over(Pref, pref)
+    lp3 = olp.assemble(case3, w, mask3)
+    Fstar = np.array([-solve_plan(lp3, j).objective for j in range(k)])
+    r3 = outs[2]
+    F3 = olp.planning_objective(case3, w, r3["t"].T, mask3)[0]
+    assert np.max(np.abs(F3 - r3["objective"]) / Fstar) < 1e-9
+    rel = np.abs(r3["objective"] - Fstar) / Fstar
+    say("pass-3 rel err", rel, "status", r3["plan_status"], "iters", r3["iters"])
+    assert np.all(rel < 1e-3), rel

@@ -188,6 +188,11 @@ def _prepare(root):
     write_inputs(d, t["case"], t["w"], "f64", 2, seed=41, vox=t["vox"], d_ld=0.05, delta=0.1,
                  tiles=(1, 3), two_pass=True)
     runs["tp2"] = d
+    t = _tp_spec()
+    d = os.path.join(root, "tp3")
+    write_inputs(d, t["case"], t["w"], "f64", 2, seed=41, vox=t["vox"], d_ld=0.05, delta=0.1,
+                 tiles=(1, 3), two_pass=3)
+    runs["tp3"] = d
     v = _serve_spec()
     d = os.path.join(root, "serve")
     write_inputs(d, v["case"], v["w"], "f32", 1, mask=v["mask"], tiles=(0, 0), serve=True)
@@ -269,13 +274,15 @@ def test_emulated_ld_mask_oar_band_and_alg1(emu):
     assert np.array_equal(band, ref)
 
 
-@pytest.mark.parametrize("run,levels", [("tp", None), ("tp2", [0.5, 0.3])])
-def test_emulated_two_pass(emu, run, levels):
-    """Both passes through ladmm_two_pass (one low-dose group) and
+@pytest.mark.parametrize("run,levels,passes", [("tp", None, 2), ("tp2", [0.5, 0.3], 2),
+                                               ("tp3", None, 3)])
+def test_emulated_two_pass(emu, run, levels, passes):
+    """Both passes through ladmm_two_pass (one low-dose group),
     ladmm_two_pass_sets (two low-dose groups with thresholds d and d / 2, App.
-    A): every set's pass-2 point set equals the oracle's band + Algorithm 1 from
-    the pass-1 shot times, and the pass-2 objective is the oracle's F of the
-    returned shot times on the rebuilt case."""
+    A) and three passes through ladmm_passes: every set's last-pass point set
+    equals the oracle's band + Algorithm 1 from the previous pass's shot times,
+    and the last pass's objective is the oracle's F of the returned shot times
+    on the rebuilt case."""
     d = finished(emu, run)
     t = _tp_spec(levels)
     case, w, cand, vox = t["case"], t["w"], t["cand"], t["vox"]
@@ -284,8 +291,8 @@ def test_emulated_two_pass(emu, run, levels):
     counts = np.fromfile(os.path.join(d, "tp_n.i64"), np.int64)
     assert len(counts) == len(ld_groups) + 1
     P_all = np.fromfile(os.path.join(d, "tp_P.i64"), np.int64)
-    t1 = rd(d, "tp_t1.f64", (k, n_t))
-    dose1 = odose.dose(vox, t1.T)
+    t_prev = rd(d, "tp_t1.f64" if passes == 2 else f"tp_tmid{passes - 1}.f64", (k, n_t))
+    dose1 = odose.dose(vox, t_prev.T)
     keep = np.nonzero(~np.isin(case.group, ld_groups))[0]
     extra, blocks, at = [], [], 0
     for i, g in enumerate(ld_groups):
