@@ -412,6 +412,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
 #pragma unroll
       for (int q = 0; q < NST; ++q) st[tm][tn][q] = 0.0;
 
+  // per-column step sizes and activity, loaded once
+  T irc[TN];
+  bool act[TN];
+#pragma unroll
+  for (int tn = 0; tn < TN; ++tn) {
+    const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
+    irc[tn] = EPI == EPI_OBJ ? T(0) : (T)ea.invrho[n];
+    act[tn] = EPI == EPI_OBJ ? false : ea.active[n] != 0;
+  }
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -438,8 +447,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
           const T z = clip0u(qv, u);
           // q' = x1 + y1 = z1 - c/rho - A_s' v, with c_p = -sign_p; the next
           // right-hand-side product needs W' = z1' - y1' = 2 clip(q') - q'
-          const T qn = z + sg * (T)ea.invrho[n] - s;
-          if (ea.active[n]) {
+          const T qn = z + sg * irc[tn] - s;
+          if (act[tn]) {
             *qp = qn;
             ea.w[(size_t)m * ea.ldq + n] = T(2) * clip0u(qn, u) - qn;
           }
