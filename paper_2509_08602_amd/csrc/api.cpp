@@ -700,7 +700,7 @@ int iterate_once(ladmm_batch *b, bool stats) {
                       kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
   PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
   PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
-                           c->nchunk2, nullptr, 1)));
+                           c->nchunk2, nullptr, b->cfg_s)));
   PROF(3, (vreduce<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (T *)b->vT)));
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
   EpiArgs<T> ea{};
@@ -758,7 +758,7 @@ int iterate_bf(ladmm_batch *b, bool stats) {
   PROF(0, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
   PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
   PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
-                           c->nchunk2, nullptr, 1)));
+                           c->nchunk2, nullptr, b->cfg_s)));
   PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
                       (uint16_t *)V.lo)));
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
@@ -872,9 +872,10 @@ template <typename T>
 int autotune(ladmm_batch *b) {
   ladmm_case *c = b->c;
   for (auto &e : c->tuned)
-    if (e.first == b->kp) {
-      b->cfg1 = e.second.first;
-      b->cfg2 = e.second.second;
+    if (e.kp == b->kp) {
+      b->cfg1 = e.cfg1;
+      b->cfg2 = e.cfg2;
+      b->cfg_s = e.cfg_s;
       b->tuned = true;
       set_row_blocks(b);
       return LADMM_OK;
@@ -904,7 +905,26 @@ int autotune(ladmm_batch *b) {
   }
   hipFree(noact);
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-  c->tuned.push_back({kp, {b->cfg1, b->cfg2}});
+  // the FP64 S^-1 r product (it writes only its split partials)
+  float best_s = 1e30f;
+  for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
+    if (!gemm_tn_cfg_ok(cfg, c->mAp, kp)) continue;
+    float tot = 0.f;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(b->ev0, s);
+      if (e == hipSuccess)
+        e = gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp, c->nchunk2,
+                            nullptr, cfg);
+      if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+      if (rep > 0) tot += ms;
+    }
+    if (tot < best_s) { best_s = tot; b->cfg_s = cfg; }
+  }
+  if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+  c->tuned.push_back({kp, b->cfg1, b->cfg2, b->cfg_s});
   b->tuned = true;
   set_row_blocks(b);
   return LADMM_OK;
@@ -933,7 +953,7 @@ int enqueue_iterations(ladmm_batch *b, int n) {
   }
   hipGraphExec_t exec = nullptr;
   for (const auto &g : b->graph_cache)
-    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2) exec = g.exec;
+    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2 && g.cfg_s == b->cfg_s) exec = g.exec;
   if (!exec) {
     if (!b->cap_stream) HIPC(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     // the launches below go to the capture stream; the graph runs on b->stream
@@ -963,7 +983,7 @@ int enqueue_iterations(ladmm_batch *b, int n) {
       hipGraphExecDestroy(b->graph_cache.front().exec);
       b->graph_cache.erase(b->graph_cache.begin());
     }
-    b->graph_cache.push_back({n, b->cfg1, b->cfg2, exec});
+    b->graph_cache.push_back({n, b->cfg1, b->cfg2, b->cfg_s, exec});
   }
   HIPC(hipGraphLaunch(exec, b->stream));
   return LADMM_OK;

@@ -90,7 +90,9 @@ struct ladmm_case {
   int nchunk1 = 1, nchunk2 = 1;
   int refs = 0;              // live batches
   bool destroyed = false;    // destroy requested while batches were alive
-  std::vector<std::pair<int, std::pair<int, int>>> tuned;   // kp -> (GEMM1, GEMM2) tiles
+  // per padded plan count: tiles of GEMM1, GEMM2 and the S^-1 product
+  struct Tuned { int kp, cfg1, cfg2, cfg_s; };
+  std::vector<Tuned> tuned;
 };
 
 struct ladmm_batch {
@@ -129,9 +131,10 @@ struct ladmm_batch {
   int chunk_active = 0;       // active plans of the chunk in flight
   // tile configurations of the two dose-matrix products (autotuned)
   int cfg1 = 0, cfg2 = 0;
+  int cfg_s = 1;              // the FP64 S^-1 r product (autotuned too)
   bool tuned = false;
   // captured iteration chunks, replayed while profiling is off
-  struct Graph { int n, cfg1, cfg2; hipGraphExec_t exec; };
+  struct Graph { int n, cfg1, cfg2, cfg_s; hipGraphExec_t exec; };
   bool graphs = true;
   std::vector<Graph> graph_cache;
   // captures run on a stream of their own that does not synchronize with the
