@@ -143,6 +143,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--alpha", type=float, default=1.0,
+                    help="over-relaxation of the sweeps (1: the paper's ADMM)")
     ap.add_argument("--warm-store", type=int, default=256,
                     help="serving: solved plans kept per case for warm starts (0: cold starts)")
     ap.add_argument("--launch", default="graph", choices=("graph", "eager"),
@@ -393,10 +395,10 @@ def main():
     sweep = None
     if not args.no_sweep:
         opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=1e-3, tol_pri=1e-3,
-                             tol_dual=1e-3, rho0=rho0, w0_bot=cases.W0_BOT)
+                             tol_dual=1e-3, rho0=rho0, w0_bot=cases.W0_BOT, alpha=args.alpha)
         t1 = time.perf_counter()
         out = ladmm.solve_batch(dc, w, opts=opts)
-        sweep = dict(plans=k, seconds=round(time.perf_counter() - t1, 4), tol_gap=1e-3,
+        sweep = dict(plans=k, seconds=round(time.perf_counter() - t1, 4), tol_gap=1e-3, alpha=args.alpha,
                      converged=int(np.sum(out["plan_status"] == ladmm.PLAN_CONVERGED)),
                      max_iters=int(out["iters"].max()), median_iters=float(np.median(out["iters"])),
                      max_rel_gap=float(out["rel_gap"].max()), passes=1)

@@ -126,6 +126,11 @@ typedef struct {
    * exact.  adapt_mu > 1, adapt_tau > 1. */
   int32_t adapt_rho;
   double adapt_mu, adapt_tau;
+  /* Over-relaxation (an extension; the paper's ADMM has alpha = 1): the z- and
+   * y-steps of Eq. (admm) use alpha x + (1 - alpha) z in place of x, z the
+   * copies before the step; the residuals keep x.  alpha in (0, 2); 0 means 1.
+   * Batches and solves only: ladmm_submit rejects alpha other than 0 or 1. */
+  double alpha;
 } ladmm_opts;
 
 /* Per-plan results; every pointer is caller-owned host memory or NULL.

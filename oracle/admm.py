@@ -65,8 +65,12 @@ def schur_factor(slp: ScaledLP):
 
 
 def admm_iterate(slp: ScaledLP, rho, iters: int, state: ADMMState | None = None,
-                 factor=None) -> ADMMState:
-    """Run `iters` iterations of Eq. (admm) from `state` (zeros if None)."""
+                 factor=None, alpha: float = 1.0) -> ADMMState:
+    """Run `iters` iterations of Eq. (admm) from `state` (zeros if None).
+
+    alpha != 1: over-relaxation (an extension; the paper uses alpha = 1): the
+    z- and y-steps take x_hat = alpha x + (1 - alpha) z in place of x, with z the
+    copies before the step.  The residuals keep the unrelaxed x."""
     rho = np.asarray(rho, np.float64).ravel()
     k = rho.size
     st = zero_state(slp, k) if state is None else state.copy()
@@ -79,11 +83,13 @@ def admm_iterate(slp: ScaledLP, rho, iters: int, state: ADMMState | None = None,
         v = linalg.cho_solve(factor, A @ W - st.z2 + st.y2)
         x1 = W - A.T @ v
         x2 = v + st.z2 - st.y2
-        z1 = np.clip(x1 + st.y1, 0.0, u)
-        z2 = np.minimum(x2 + st.y2, b)
+        x1h = x1 if alpha == 1.0 else alpha * x1 + (1.0 - alpha) * st.z1
+        x2h = x2 if alpha == 1.0 else alpha * x2 + (1.0 - alpha) * st.z2
+        z1 = np.clip(x1h + st.y1, 0.0, u)
+        z2 = np.minimum(x2h + st.y2, b)
         st.z1_prev, st.z2_prev = st.z1, st.z2
-        st.y1 = st.y1 + x1 - z1
-        st.y2 = st.y2 + x2 - z2
+        st.y1 = st.y1 + x1h - z1
+        st.y2 = st.y2 + x2h - z2
         st.z1, st.z2, st.x1, st.x2 = z1, z2, x1, x2
         st.iterations += 1
     return st
@@ -122,7 +128,7 @@ def residuals(slp: ScaledLP, rho, state: ADMMState):
 
 def admm_adaptive(slp: ScaledLP, rho, iters: int, check_every: int, mu: float = 10.0,
                   tau: float = 2.0, rho_range: float = 1e3, state: ADMMState | None = None,
-                  factor=None):
+                  factor=None, alpha: float = 1.0):
     """Eq. (admm) with per-plan step sizes balanced at every check.
 
     The step sizes start from the rule of Sec. 3.C (rho) and, after every
@@ -142,7 +148,7 @@ def admm_adaptive(slp: ScaledLP, rho, iters: int, check_every: int, mu: float = 
     done = 0
     while done < iters:
         n = min(check_every, iters - done)
-        st = admm_iterate(slp, rho, n, st, factor)
+        st = admm_iterate(slp, rho, n, st, factor, alpha)
         done += n
         if n < check_every:
             break

@@ -114,6 +114,7 @@ SmallArgs small_args(const ladmm_batch *b) {
   a.bbot = b->bbot;
   a.active = b->active;
   a.kp = b->kp;
+  a.alpha = b->alpha;
   return a;
 }
 
@@ -558,6 +559,8 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   if (opts->adapt_rho && (!(opts->adapt_mu > 1) || !(opts->adapt_tau > 1) ||
                           !std::isfinite(opts->adapt_mu) || !std::isfinite(opts->adapt_tau)))
     return fail(LADMM_E_INVALID, "adapt_mu and adapt_tau must be finite and > 1");
+  if (opts->alpha != 0.0 && !(opts->alpha > 0.0 && opts->alpha < 2.0))
+    return fail(LADMM_E_INVALID, "alpha must be in (0, 2) (0 selects 1)");
 
   {
     int rc = case_ref(c);
@@ -569,6 +572,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   b->k = slots ? b->kp : k;
   k = b->k;
   b->opts = *opts;
+  b->alpha = opts->alpha == 0.0 ? 1.0 : opts->alpha;
   if (slots)
     b->w.assign(k, ladmm_weights{0.0, 0.0, 0.0, 1.0});
   else
@@ -712,6 +716,7 @@ int iterate_once(ladmm_batch *b, bool stats) {
   ea.stats = b->admm_stats;
   ea.nstat_cols = kp;
   ea.pt = pt;
+  ea.alpha = b->alpha;
   PROF(4, (gemm_nn<T>(s, stats ? EPI_ADMM_STATS : EPI_ADMM, (const T *)c->D, c->ntp,
                       (const T *)b->vT, kp, c->Np, kp, c->ntp, ea, b->cfg2)));
   if (stats) {
@@ -773,6 +778,7 @@ int iterate_bf(ladmm_batch *b, bool stats) {
   ea.wt_hi = (uint16_t *)W.hi;
   ea.wt_lo = (uint16_t *)W.lo;
   ea.ldwt = c->Np;
+  ea.alpha = b->alpha;
   PROF(4, (gemm_bf_nn(s, stats ? EPI_ADMM_STATS : EPI_ADMM, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2)));
   if (stats) {
     const BfPair Tt = plan_pairs(b->that, kp, c->ntp);
@@ -846,6 +852,7 @@ hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact)
     ea.wt_hi = (uint16_t *)b->W;
     ea.wt_lo = (uint16_t *)b->W + (size_t)kp * c->Np;
     ea.ldwt = c->Np;
+    ea.alpha = b->alpha;
     return gemm_bf_nn(s, EPI_ADMM, Dp, plan_pairs(b->vT, kp, c->ntp), c->Np, kp, c->ntp, ea, 3, cfg);
   }
   if (which == 0)
@@ -858,6 +865,7 @@ hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact)
   ea.invrho = b->invrho;
   ea.active = noact;
   ea.pt = point_table<T>(b);
+  ea.alpha = b->alpha;
   return gemm_nn<T>(s, EPI_ADMM, (const T *)c->D, c->ntp, (const T *)b->vT, kp, c->Np, kp, c->ntp,
                     ea, cfg);
 }

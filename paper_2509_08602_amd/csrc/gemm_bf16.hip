@@ -171,7 +171,9 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
         } else {
           const float qv = qv4[r];
           const float z = clip0u_f(qv, u);
-          const float qn = z + sg * irc[tn] - s;
+          const float qx = z + sg * irc[tn] - s;   // x + y of the closed-form x-step
+          // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
+          const float qn = ea.alpha == 1.0 ? qx : qv + (float)ea.alpha * (qx - qv);
           const float wv = 2.f * clip0u_f(qn, u) - qn;
           split_pair((double)wv, wh[r], wl[r]);
           if (act[tn]) ea.q[(size_t)m * ea.ldq + n] = qn;
@@ -179,8 +181,9 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
             const double yo = (double)qv - (double)z;
             const double zn = (double)clip0u_f(qn, u);
             const double yn = (double)qn - zn;
-            const double x = (double)qn - yo;
-            const double dxz = yn - yo, dz = zn - (double)z;
+            const double x = (double)qx - yo;
+            // x - z' (the unrelaxed x); without relaxation y' - y is the same value
+            const double dxz = ea.alpha == 1.0 ? yn - yo : x - zn, dz = zn - (double)z;
             st[0] = fma(dxz, dxz, st[0]);
             st[1] = fma(x, x, st[1]);
             st[2] = fma(zn, zn, st[2]);

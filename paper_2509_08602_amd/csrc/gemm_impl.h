@@ -447,7 +447,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
           const T z = clip0u(qv, u);
           // q' = x1 + y1 = z1 - c/rho - A_s' v, with c_p = -sign_p; the next
           // right-hand-side product needs W' = z1' - y1' = 2 clip(q') - q'
-          const T qn = z + sg * irc[tn] - s;
+          const T qx = z + sg * irc[tn] - s;     // x + y of the closed-form x-step
+          // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
+          const T qn = ea.alpha == 1.0 ? qx : qv + (T)ea.alpha * (qx - qv);
           if (act[tn]) {
             *qp = qn;
             ea.w[(size_t)m * ea.ldq + n] = T(2) * clip0u(qn, u) - qn;
@@ -456,8 +458,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
             const double yo = (double)qv - (double)z;
             const double zn = (double)clip0u(qn, u);
             const double yn = (double)qn - zn;
-            const double x = (double)qn - yo;
-            const double dxz = yn - yo, dz = zn - (double)z;
+            const double x = (double)qx - yo;
+            // x - z' (the unrelaxed x); without relaxation y' - y is the same value
+            const double dxz = ea.alpha == 1.0 ? yn - yo : x - zn, dz = zn - (double)z;
             // explicit fused multiply-adds: the compiler's contraction choices
             // may differ between configurations, these may not
             st[tm][tn][0] = fma(dxz, dxz, st[tm][tn][0]);   // (x - z')^2

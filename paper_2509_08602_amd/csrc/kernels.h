@@ -60,6 +60,7 @@ struct EpiArgs {
   double *stats; int nstat_cols;   // partial stats [blockIdx.x][stat][nstat_cols]
   PointTable<T> pt;
   uint16_t *wt_hi, *wt_lo; int ldwt;   // BF16-pair products: W' = z1' - y1' as plans x points
+  double alpha;                    // over-relaxation of the z- and y-steps (1: none)
 };
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb,
@@ -95,6 +96,7 @@ struct SmallArgs {
   const double *bbot;   // n_iso x kp: scaled BOT bound E_bot * w_BOT
   const int32_t *active;
   int kp;
+  double alpha;         // over-relaxation of the z- and y-steps (1: none)
 };
 // r = A_s W + g / rho - (2 clip(q2) - q2), from the GEMM1 partials.
 template <typename T>

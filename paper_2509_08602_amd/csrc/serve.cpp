@@ -741,6 +741,8 @@ int ladmm_submit(ladmm_server *sv, ladmm_case *c, int32_t k, const ladmm_weights
   if (opts->check_every != 0 && opts->check_every != sv->opts.check_every)
     return fail(LADMM_E_INVALID, "submit: check_every must be 0 or the server's");
   if (!(opts->rho0 > 0) || !(opts->w0_bot > 0)) return fail(LADMM_E_INVALID, "submit: rho0 and w0_bot must be > 0");
+  if (opts->alpha != 0.0 && opts->alpha != 1.0)
+    return fail(LADMM_E_INVALID, "submit: served plans run without over-relaxation (alpha 0 or 1)");
   if (opts->adapt_rho && (!(opts->adapt_mu > 1) || !(opts->adapt_tau > 1) ||
                           !std::isfinite(opts->adapt_mu) || !std::isfinite(opts->adapt_tau)))
     return fail(LADMM_E_INVALID, "submit: adapt_mu and adapt_tau must be finite and > 1");

@@ -407,7 +407,7 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ v, double *__rest
   for (int rr = threadIdx.y; valid && rr < kPostRows; rr += 4) {
     const int m = blockIdx.x * kPostRows + rr;
     if (m >= total) break;
-    double qv, z, qn, bnd;
+    double qv, z, qx, qn, bnd;
     const bool sector = m >= L.mAp;
     if (!sector) {
       const bool top = m < L.n_t;
@@ -416,7 +416,8 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ v, double *__rest
       bnd = top ? 0.0 : a.bbot[(size_t)(m - L.ntp) * kp + j];
       qv = q2[(size_t)m * kp + j];
       z = fmin(qv, bnd);
-      qn = v[(size_t)m * kp + j] + z;                        // x2 + y2 = v + z2
+      qx = v[(size_t)m * kp + j] + z;                        // x2 + y2 = v + z2
+      qn = a.alpha == 1.0 ? qx : qv + a.alpha * (qx - qv);   // over-relaxed
       if (act) q2[(size_t)m * kp + j] = qn;
     } else {
       const int sec = m - L.mAp;
@@ -430,7 +431,8 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ v, double *__rest
       atv += a.beta * a.E[mb] * v[(size_t)mb * kp + j];
       qv = qs[(size_t)sec * kp + j];
       z = fmax(qv, 0.0);
-      qn = z - atv;                                          // c = 0, u = +inf here
+      qx = z - atv;                                          // c = 0, u = +inf here
+      qn = a.alpha == 1.0 ? qx : qv + a.alpha * (qx - qv);   // over-relaxed
       if (act) qs[(size_t)sec * kp + j] = qn;
       bnd = INFINITY;
     }
@@ -438,8 +440,9 @@ __global__ void k_post(SmallArgs a, const double *__restrict__ v, double *__rest
       const double yo = qv - z;
       const double zn = sector ? fmax(qn, 0.0) : fmin(qn, bnd);
       const double yn = qn - zn;
-      const double x = qn - yo;
-      st[0] += (yn - yo) * (yn - yo);
+      const double x = qx - yo;
+      const double dxz = a.alpha == 1.0 ? yn - yo : x - zn;   // x - z', unrelaxed x
+      st[0] += dxz * dxz;
       st[1] += x * x;
       st[2] += zn * zn;
       st[3] += (zn - z) * (zn - z);

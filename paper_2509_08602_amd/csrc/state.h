@@ -132,6 +132,7 @@ struct ladmm_batch {
   // tile configurations of the two dose-matrix products (autotuned)
   int cfg1 = 0, cfg2 = 0;
   int cfg_s = 1;              // the FP64 S^-1 r product (autotuned too)
+  double alpha = 1.0;         // over-relaxation of the z- and y-steps
   bool tuned = false;
   // captured iteration chunks, replayed while profiling is off
   struct Graph { int n, cfg1, cfg2, cfg_s; hipGraphExec_t exec; };

@@ -54,7 +54,7 @@ class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("tol_gap", C.c_double),
                 ("tol_pri", C.c_double), ("tol_dual", C.c_double), ("rho0", C.c_double),
                 ("w0_bot", C.c_double), ("autotune", C.c_int32), ("adapt_rho", C.c_int32),
-                ("adapt_mu", C.c_double), ("adapt_tau", C.c_double)]
+                ("adapt_mu", C.c_double), ("adapt_tau", C.c_double), ("alpha", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -207,12 +207,13 @@ class Options:
     adapt_rho: bool = True
     adapt_mu: float = 10.0
     adapt_tau: float = 2.0
+    alpha: float = 1.0         # over-relaxation (1: the paper's ADMM)
 
     def c(self):
         return _Opts(int(self.max_iter), int(self.check_every), float(self.tol_gap),
                      float(self.tol_pri), float(self.tol_dual), float(self.rho0),
                      float(self.w0_bot), 1 if self.autotune else 0, 1 if self.adapt_rho else 0,
-                     float(self.adapt_mu), float(self.adapt_tau))
+                     float(self.adapt_mu), float(self.adapt_tau), float(self.alpha))
 
 
 class Context:

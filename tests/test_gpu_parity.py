@@ -91,6 +91,35 @@ def test_iterations_match_oracle_c0(ctx, c0, precision, tol1, tol50):
             assert err < tol, f"{precision} after {done} iterations: {name} rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("precision,tol1,tol50", [("f64", 1e-12, 1e-9), ("f32", 2e-5, 5e-4),
+                                                   ("bf16x3", 5e-5, 1e-3)])
+def test_over_relaxed_iterations_match_oracle_c0(ctx, c0, precision, tol1, tol50):
+    """alpha = 1.6: the relaxed z- and y-steps on the device follow the oracle's
+    over-relaxed ADMM element by element, in the fixed-rule setting."""
+    say("over-relaxed iteration parity c0", precision)
+    w = cases.config_weights(0)
+    _, slp, rho = oracle_setup(c0, w)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False,
+                                              alpha=1.6))
+    fac, _ = oadmm.schur_factor(slp)
+    st = None
+    done = 0
+    for n, tol in ((1, tol1), (49, tol50)):
+        b.iterate(n)
+        st = oadmm.admm_iterate(slp, rho, n, st, fac, alpha=1.6)
+        done += n
+        z1, y1, z2, y2 = b.export()
+        for name, got, ref in (("z1", z1, st.z1), ("y1", y1, st.y1), ("z2", z2, st.z2),
+                               ("y2", y2, st.y2)):
+            err = rel_err(got, ref)
+            assert err < tol, f"{precision} after {done} iterations: {name} rel err {err:.3e}"
+    # the check statistics use the unrelaxed x, as the oracle's residuals
+    res = b.results()
+    r_pri, r_dual = oadmm.residuals(slp, rho, st)
+    assert rel_err(res["r_pri"], r_pri) < (1e-8 if precision == "f64" else 5e-2)
+
+
 def test_import_export_roundtrip_and_resume(ctx, c0):
     say("import/export resume c0 f64")
     w = cases.config_weights(0)[[1, 5, 6]]

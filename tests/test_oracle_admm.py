@@ -147,3 +147,25 @@ def test_adaptive_rho_recovers_from_a_poor_start():
     err, err_fixed = np.abs(F - Fstar) / Fstar, np.abs(F_fixed - Fstar) / Fstar
     assert np.all(err < 3e-3), err
     assert err_fixed.max() > 5 * err.max()
+
+
+def test_over_relaxed_admm_reaches_the_simplex_optimum():
+    """Over-relaxed ADMM (alpha = 1.6) has the same fixed points: every plan of the
+    small case reaches the exact LP optimum of the simplex within 1e-3."""
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    lp = olp.assemble(case, w)
+    Fstar = np.array([-solve_plan(lp, j).objective for j in range(w.shape[0])])
+    slp = olp.precondition(lp, olp.bot_scale(case))
+    rho = olp.rho_rule(w[:, 3], 1000.0, cases.W0_BOT)
+    fac, _ = admm.schur_factor(slp)
+    st = None
+    best = np.full(w.shape[0], np.inf)
+    for _ in range(40):
+        st = admm.admm_iterate(slp, rho, 100, st, fac, alpha=1.6)
+        t, _ = admm.shot_times(slp, rho, st)
+        F = olp.planning_objective(case, w, t)[0]
+        best = np.minimum(best, np.abs(F - Fstar) / Fstar)
+    assert np.all(best < 1e-3), best
+    r_pri, r_dual = admm.residuals(slp, rho, st)
+    assert np.all(r_pri < 1e-3) and np.all(r_dual < 1e-3)
