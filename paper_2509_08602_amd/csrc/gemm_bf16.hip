@@ -81,9 +81,19 @@ template <int MODE>
 constexpr int bf_nstat() { return MODE == EPI_OBJ ? kObjStats : kAdmmStats; }
 template <int MODE>
 constexpr bool bf_has_stats() { return MODE == EPI_ADMM_STATS || MODE == EPI_OBJ; }
-// LDS of the statistics partials: one per 16-row tile, statistic and column.
+// LDS of the epilogue: the statistics partials (one per 16-row tile, statistic
+// and column), then, when W' is written, its hi and lo halves staged as
+// BN columns of BM rows (padded by 8 elements, 16-byte aligned columns) so that
+// each plan's rows leave as contiguous 16-byte pieces.
 template <int BM, int BN, int MODE>
-constexpr size_t bf_red_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
+constexpr size_t bf_stat_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
+template <int BM>
+constexpr int bf_wstage_ld() { return BM + 8; }
+template <int BM, int BN, int MODE>
+constexpr size_t bf_red_bytes() {
+  return bf_stat_bytes<BM, BN, MODE>() +
+         (MODE == EPI_ADMM || MODE == EPI_ADMM_STATS ? 2 * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
+}
 
 __device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
 
@@ -120,6 +130,10 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
     return;
   }
   auto sred = reinterpret_cast<double (*)[NST][BN]>(smem);
+  constexpr int LDW = bf_wstage_ld<BM>();
+  auto swh = reinterpret_cast<uint16_t (*)[LDW]>(smem + bf_stat_bytes<BM, BN, MODE>());
+  auto swl = reinterpret_cast<uint16_t (*)[LDW]>(smem + bf_stat_bytes<BM, BN, MODE>() +
+                                                  sizeof(uint16_t) * BN * LDW);
   // per-row (group, sign) and per-column (1/rho, active) values, loaded once
   int grow[TM][4];
   float srow[TM][4];
@@ -193,11 +207,12 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           }
         }
       }
-      if (MODE != EPI_OBJ && act[tn]) {
-        const size_t o = (size_t)n * ea.ldwt + mb;
-        *reinterpret_cast<uint2 *>(ea.wt_hi + o) =
+      if (MODE != EPI_OBJ) {
+        // staged: column n - n0, rows mb - m0 .. + 3
+        const int cl = n - n0, rl = mb - m0;
+        *reinterpret_cast<uint2 *>(&swh[cl][rl]) =
             uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
-        *reinterpret_cast<uint2 *>(ea.wt_lo + o) =
+        *reinterpret_cast<uint2 *>(&swl[cl][rl]) =
             uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
       }
       if (kStats) {
@@ -215,8 +230,20 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
         }
       }
     }
-  if (!kStats) return;
+  if (MODE == EPI_OBJ && !kStats) return;
   __syncthreads();
+  if (MODE != EPI_OBJ) {
+    // W' of the active plans: each column's BM rows as 16-byte pieces, in order
+    for (int e = tid; e < BN * (BM / 8); e += NT) {
+      const int cl = e / (BM / 8), ch = (e % (BM / 8)) * 8;
+      const int n = n0 + cl;
+      if (!ea.active[n]) continue;
+      const size_t o = (size_t)n * ea.ldwt + m0 + ch;
+      *reinterpret_cast<uint4 *>(ea.wt_hi + o) = *reinterpret_cast<const uint4 *>(&swh[cl][ch]);
+      *reinterpret_cast<uint4 *>(ea.wt_lo + o) = *reinterpret_cast<const uint4 *>(&swl[cl][ch]);
+    }
+  }
+  if (!kStats) return;
   for (int e = tid; e < (BM / 32) * NST * BN; e += NT) {
     const int b = e / (NST * BN), q = (e / BN) % NST, c = e % BN;
     const double t0 = sred[2 * b][q][c], t1 = sred[2 * b + 1][q][c];
