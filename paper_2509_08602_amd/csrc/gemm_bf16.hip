@@ -82,17 +82,20 @@ constexpr int bf_nstat() { return MODE == EPI_OBJ ? kObjStats : kAdmmStats; }
 template <int MODE>
 constexpr bool bf_has_stats() { return MODE == EPI_ADMM_STATS || MODE == EPI_OBJ; }
 // LDS of the epilogue: the statistics partials (one per 16-row tile, statistic
-// and column), then, when W' is written, its hi and lo halves staged as
-// BN columns of BM rows (padded by 8 elements, 16-byte aligned columns) so that
-// each plan's rows leave as contiguous 16-byte pieces.
+// and column); in the plain ADMM epilogue, W' hi and lo halves staged as BN
+// columns of BM rows (padded by 8 elements, 16-byte aligned columns) so that
+// each plan's rows leave as contiguous 16-byte pieces.  The statistics variant
+// (one launch per convergence check) stores W' directly instead: staging on top
+// of its partials would halve its occupancy.
 template <int BM, int BN, int MODE>
 constexpr size_t bf_stat_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
 template <int BM>
 constexpr int bf_wstage_ld() { return BM + 8; }
+template <int MODE>
+constexpr bool bf_wstaged() { return MODE == EPI_ADMM; }
 template <int BM, int BN, int MODE>
 constexpr size_t bf_red_bytes() {
-  return bf_stat_bytes<BM, BN, MODE>() +
-         (MODE == EPI_ADMM || MODE == EPI_ADMM_STATS ? 2 * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
+  return bf_stat_bytes<BM, BN, MODE>() + (bf_wstaged<MODE>() ? 2 * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
 }
 
 __device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
@@ -207,12 +210,18 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           }
         }
       }
-      if (MODE != EPI_OBJ) {
+      if (bf_wstaged<MODE>()) {
         // staged: column n - n0, rows mb - m0 .. + 3
         const int cl = n - n0, rl = mb - m0;
         *reinterpret_cast<uint2 *>(&swh[cl][rl]) =
             uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
         *reinterpret_cast<uint2 *>(&swl[cl][rl]) =
+            uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
+      } else if (MODE == EPI_ADMM_STATS && act[tn]) {
+        const size_t o = (size_t)n * ea.ldwt + mb;
+        *reinterpret_cast<uint2 *>(ea.wt_hi + o) =
+            uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
+        *reinterpret_cast<uint2 *>(ea.wt_lo + o) =
             uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
       }
       if (kStats) {
@@ -232,7 +241,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
     }
   if (MODE == EPI_OBJ && !kStats) return;
   __syncthreads();
-  if (MODE != EPI_OBJ) {
+  if (bf_wstaged<MODE>()) {
     // W' of the active plans: each column's BM rows as 16-byte pieces, in order
     for (int e = tid; e < BN * (BM / 8); e += NT) {
       const int cl = e / (BM / 8), ch = (e % (BM / 8)) * 8;
