@@ -47,9 +47,13 @@ COPY_PROBE_BYTES = 256 << 20
 # HBM traffic per launch of the dose-matrix products, from rocprofv3 counter
 # runs (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); valid
 # only while the kernels' sources are the ones that were measured.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_c1_f32_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_08602_amd", "csrc", f)
-                  for f in ("gemm_impl.h", "gemm_f32.hip", "kernels.h")]
+# One record per product precision: the file and the sources its kernels come from.
+TRAFFIC = {
+    "f32": (os.path.join(ROOT, "profiles", "gemm_c1_f32_traffic.txt"),
+            ("gemm_impl.h", "gemm_f32.hip", "kernels.h")),
+    "bf16x3": (os.path.join(ROOT, "profiles", "gemm_c2_bf16_traffic.txt"),
+               ("gemm_bf16.hip", "kernels.h")),
+}
 
 
 def copy_probe():
@@ -101,26 +105,26 @@ def two_pass_sweep(ctx, case, w, precision, opts, max_vox=60000):
                 pass2_max_iters=int(r2["iters"].max()))
 
 
-def kernel_source_hash():
+def kernel_source_hash(precision):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in TRAFFIC[precision][1]:
+        h.update(open(os.path.join(ROOT, "paper_2509_08602_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, config_name):
+def measured_traffic(kernel, config_name, precision):
     """Bytes per launch recorded for `kernel` on this workload, or None."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if precision not in TRAFFIC or not os.path.exists(TRAFFIC[precision][0]):
         return None
     rec = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(TRAFFIC[precision][0]):
         line = line.strip()
         if line.startswith("#") or "=" not in line:
             continue
         key, val = line.split("=", 1)
         rec[key.strip()] = val.strip()
-    if rec.get("source_hash") != kernel_source_hash() or rec.get("workload") != config_name:
+    if rec.get("source_hash") != kernel_source_hash(precision) or rec.get("workload") != config_name:
         return None
     v = rec.get(f"{kernel}_bytes_per_launch")
     return float(v) if v else None
@@ -383,7 +387,7 @@ def main():
     avg_ms = tot / max(cnt, 1)
     achieved = flops_gemm / (avg_ms * 1e-3) / 1e12
     peak = PEAKS[precision]
-    traffic = measured_traffic(dom, case.name) if precision == "f32" else None
+    traffic = measured_traffic(dom, case.name, precision)
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
                     avg_launch_ms=round(avg_ms, 5),
