@@ -1,24 +1,31 @@
 """Benchmark: batched ADMM plan-iterations/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
 
-Workload (default): the medium multi-target case, three targets, N = 40,000
-dose points x 1,440 shot columns (60 isocentres x 8 sectors x 3 collimators),
-81 plans from a 9 x 9 slider grid, FP32 dose block and iterates, FP64 Schur
-complement inverse and small side.  The case is built and made resident in HBM
-before timing (the setup time is reported beside the result).
+Workload (default): the large case, nine targets, N = 200,000 dose points x
+4,800 shot columns (200 isocentres x 8 sectors x 3 collimators), 441 plans from
+a 21 x 21 slider grid, solved with the BF16 dose block and iterative
+refinement (precision mode bf16: single BF16 products of the change since the
+last refresh, a three-term pair refresh every check, FP32 iterates, FP64 Schur
+complement inverse and small side).  The case is built and made resident in
+HBM before timing (the setup time is reported beside the result).
 
-A step is one pass of the whole iteration path over the 81-plan batch: 50 ADMM
-iterations (right-hand-side product, Schur solve, small-side update, closed-form
-x-step with the fused z- and y-steps) followed by one convergence check (the
-planning objective of the current shot times, the duality gap and the
-primal/dual residuals of every plan).  Plans are not frozen during the timed
-steps, so every step does the same work.  value = plans x iterations / time.
+A step is one pass of the whole iteration path over the 441-plan batch: 50
+ADMM iterations (right-hand-side product, Schur solve, small-side update,
+closed-form x-step with the fused z- and y-steps; the last one a refresh)
+followed by one convergence check (the planning objective of the current shot
+times, the duality gap, the certified lower bound and the primal/dual
+residuals of every plan).  Plans are not frozen during the timed steps, so
+every step does the same work.  value = plans x iterations / time.
 
 Beside it: per-kernel device times from HIP events on the solver's stream over
-the timed region (the roofline entry uses the dominant kernel), the FP64 CPU
-oracle timed on a bounded sample of the same workload, and the wall time of a
-full 81-plan sweep solved to a 1e-3 relative gap.
+the timed steps (the roofline entry uses the dominant dose-matrix product,
+counting the method's own 2 N n_t k flops per product), the FP64 CPU oracle
+timed on a bounded sample of the same workload, the wall time of the 441-plan
+sweep solved until every plan's certified gap is <= 1e-3 (its objective
+provably within 1e-3 of the exact optimum) with residuals <= 1e-4, both passes
+of Sec. 2.C under the same rule, and the plain FP64 GPU ADMM on the same GPU
+under the same rule.
 """
 from __future__ import annotations
 
@@ -38,9 +45,14 @@ PEAKS = {  # MI355X published dense peaks (TFLOP/s)
     "f64": 78.6,
     "f32": 157.3,
     "bf16x3": 2500.0,    # the BF16 matrix cores
+    "bf16": 2500.0,
 }
+HBM_PEAK_GBS = 8000.0
 # MFMA passes per dose-matrix product: the BF16-pair product executes three
-TERMS = {"f64": 1, "f32": 1, "bf16x3": 3}
+TERMS = {"f64": 1, "f32": 1, "bf16x3": 3, "bf16": 1}
+# bytes per dose-block entry read by one product in the hot iterations
+DOSE_BYTES = {"f64": 8, "f32": 4, "bf16x3": 8, "bf16": 2}
+DEFAULT_PRECISION = {0: "f64", 1: "f32", 2: "bf16"}
 ITERS_PER_STEP = 50
 RHO0 = 1e4      # step-size rule constant (Eq. rho_rule), from a grid over 30..1e4
 COPY_PROBE_BYTES = 256 << 20
@@ -133,13 +145,17 @@ def measured_traffic(kernel, config_name, precision):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-f64-sweep", action="store_true",
+                    help="skip the plain FP64 GPU ADMM sweep of the same case")
+    ap.add_argument("--tol-cert", type=float, default=1e-3,
+                    help="certified gap at which a sweep plan stops (with residuals <= 1e-4)")
     ap.add_argument("--workload", default="step", choices=("step", "uneven", "serve"),
                     help="step: iterations of one configuration (default); uneven: 32 cases "
                          "of uneven size served together; serve: Poisson request arrivals")
@@ -156,28 +172,58 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(case, w, rho0, budget_s):
-    """The FP64 oracle ADMM on the host cores, on a bounded sample of iterations."""
+def host_cpu():
+    """Host cores and model of the machine running the oracle (nproc, lscpu)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                               "CPU(s)"):
+                info[key.strip()] = val.strip()
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(case, w, rho0, budget_s, gpu_plan_iterations=None):
+    """The FP64 oracle ADMM on the host cores, on a bounded sample of iterations
+    of every plan (at least one after a warm-up iteration; setup excluded)."""
     from threadpoolctl import threadpool_info
     from oracle import lp as olp
     from oracle import admm as oadmm
     from synth import cases
+    t_setup = time.perf_counter()
     lp = olp.assemble(case, w)
     slp = olp.precondition(lp, olp.bot_scale(case))
+    del lp
     rho = olp.rho_rule(w[:, 3], rho0, cases.W0_BOT)
     fac, _ = oadmm.schur_factor(slp)
     st = oadmm.admm_iterate(slp, rho, 1, factor=fac)     # warm-up
+    setup_s = time.perf_counter() - t_setup
     iters = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        st = oadmm.admm_iterate(slp, rho, 2, st, fac)
-        iters += 2
+    while iters == 0 or time.perf_counter() - t0 < budget_s:
+        st = oadmm.admm_iterate(slp, rho, 1, st, fac)
+        iters += 1
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    return dict(value=iters * w.shape[0] / dt, unit="plan-iterations/s", cores=int(threads),
-                kind="oracle",
-                sample=f"{iters} FP64 reference-ADMM iterations x {w.shape[0]} plans of the "
-                       f"same case ({dt:.1f} s; setup excluded)")
+    value = iters * w.shape[0] / dt
+    out = dict(value=value, unit="plan-iterations/s", cores=int(threads), kind="oracle",
+               sample=f"{iters} FP64 reference-ADMM iterations x {w.shape[0]} plans of the same "
+                      f"case ({dt:.1f} s; setup {setup_s:.1f} s excluded)",
+               host=host_cpu())
+    if gpu_plan_iterations:
+        out["sweep_seconds_extrapolated"] = round(gpu_plan_iterations / value, 1)
+        out["sweep_note"] = ("the GPU sweep's plan-iterations at this oracle rate: extrapolated, "
+                             "not run")
+    return out
 
 
 def uneven(args):
@@ -324,6 +370,41 @@ def serve(args):
         "hbm_gb": round(ctx.used_bytes / 1e9, 2)}))
 
 
+def product_bytes(kernel, precision, N, n_t, k, kp):
+    """Algorithmic HBM bytes of one launch of a hot dose-matrix product: the
+    dose block once at its storage width, the plan-side operand, and the
+    result (GEMM1: the n_t x k right-hand side once; GEMM2: the epilogue's
+    iterate traffic), per padded plan column as the kernels move them."""
+    s_it = 8 if precision == "f64" else 4
+    dose = DOSE_BYTES[precision] * N * n_t
+    if precision == "bf16":
+        operand = 2 * N * kp if kernel == "gemm1" else 2 * n_t * kp
+        # q read + written, X_ref and W_ref read, dW written
+        epi = (4 * 4 + 2) * N * kp if kernel == "gemm2" else 4 * n_t * kp
+    elif precision == "bf16x3":
+        operand = 4 * N * kp if kernel == "gemm1" else 4 * n_t * kp
+        epi = (2 * 4 + 4) * N * kp if kernel == "gemm2" else 4 * n_t * kp
+    else:
+        operand = s_it * (N if kernel == "gemm1" else n_t) * kp
+        epi = 3 * s_it * N * kp if kernel == "gemm2" else s_it * n_t * kp
+    return float(dose + operand + epi)
+
+
+def sweep(dc, w, opts, label):
+    from paper_2509_08602_amd import ladmm
+    t1 = time.perf_counter()
+    out = ladmm.solve_batch(dc, w, opts=opts)
+    sec = time.perf_counter() - t1
+    conv = out["plan_status"] == ladmm.PLAN_CONVERGED
+    return dict(label=label, plans=int(w.shape[0]), seconds=round(sec, 4),
+                converged=int(conv.sum()), max_iters=int(out["iters"].max()),
+                median_iters=float(np.median(out["iters"])),
+                plan_iterations=int(out["iters"].sum()),
+                max_cert_gap=float(np.nanmax(out["cert_gap"])),
+                max_rel_gap=float(out["rel_gap"].max()), max_r_pri=float(out["r_pri"].max()),
+                max_r_dual=float(out["r_dual"].max()))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -337,8 +418,10 @@ def main():
     from paper_2509_08602_amd import ladmm
 
     cfg = args.config
-    precision = args.precision or {0: "f64", 1: "f32", 2: "bf16x3"}[cfg]
+    precision = args.precision or DEFAULT_PRECISION[cfg]
+    t_case = time.perf_counter()
     case = cases.make_case(cfg)
+    case_s = time.perf_counter() - t_case
     w = cases.config_weights(cfg)
     k = w.shape[0]
     rho0 = RHO0
@@ -371,6 +454,7 @@ def main():
     wall_eager = timed(args.steps)
     tiles = b.tiles()
     res = b.results(with_t=False)
+    kp = -(-k // 32) * 32
     b.close()
     ms_per_step = wall * 1000.0 / args.steps
     value = k * ITERS_PER_STEP * args.steps / wall
@@ -378,44 +462,75 @@ def main():
                     "eager": round(k * ITERS_PER_STEP * args.steps / wall_eager, 1),
                     "eager_with_kernel_events": round(k * ITERS_PER_STEP * args.steps / wall_prof, 1)}
 
-    # roofline of the dominant kernel (by accumulated device time): the
-    # product's flops for the k plans (2 N n_t k per MFMA pass) per launch
+    # roofline of the dominant hot dose-matrix product (by accumulated device
+    # time): the method's own flops, 2 N n_t k per product for the k plans, and
+    # its algorithmic bytes; the bound is the resource its algorithmic work
+    # needs more time on at peak
     N, n_t = case.n_points, case.n_t
-    flops_gemm = 2.0 * N * n_t * k * TERMS[precision]
+    flops_gemm = 2.0 * N * n_t * k
     dom = max(("gemm1", "gemm2"), key=lambda c: ktimes[c][0])
     tot, cnt = ktimes[dom]
     avg_ms = tot / max(cnt, 1)
-    achieved = flops_gemm / (avg_ms * 1e-3) / 1e12
     peak = PEAKS[precision]
+    rows = {}
+    for kern in ("gemm1", "gemm2"):
+        kt, kc = ktimes[kern]
+        if not kc:
+            continue
+        a_ms = kt / kc
+        byt = product_bytes(kern, precision, N, n_t, k, kp)
+        rows[kern] = dict(avg_launch_ms=round(a_ms, 5), tflops=round(flops_gemm / (a_ms * 1e-3) / 1e12, 2),
+                          mfma_frac=round(flops_gemm / (a_ms * 1e-3) / 1e12 / peak, 4),
+                          algorithmic_bytes=byt,
+                          hbm_gbs=round(byt / (a_ms * 1e-3) / 1e9, 1),
+                          hbm_frac=round(byt / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    r = rows[dom]
+    t_mfma = flops_gemm / (peak * 1e12)
+    t_hbm = r["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
     traffic = measured_traffic(dom, case.name, precision)
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=traffic, kernel=dom,
-                    avg_launch_ms=round(avg_ms, 5),
-                    algorithmic_flops_per_launch=flops_gemm, mfma_passes=TERMS[precision])
+    if t_mfma >= t_hbm:
+        roofline = dict(bound="mfma", achieved=r["tflops"], peak=peak, unit="TFLOP/s",
+                        frac=r["mfma_frac"])
+    else:
+        roofline = dict(bound="hbm", achieved=r["hbm_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=r["hbm_frac"])
+    roofline.update(traffic=traffic, kernel=dom, avg_launch_ms=round(avg_ms, 5),
+                    algorithmic_flops_per_launch=flops_gemm,
+                    algorithmic_bytes_per_launch=r["algorithmic_bytes"],
+                    mfma_frac=r["mfma_frac"], hbm_frac=r["hbm_frac"],
+                    mfma_passes=TERMS[precision], products=rows)
     kernels = {c: dict(total_ms=round(v[0], 3), launches=v[1],
                        avg_ms=round(v[0] / v[1], 5) if v[1] else None)
                for c, v in ktimes.items()}
 
-    sweep = None
+    sweeps = None
+    gpu_plan_iterations = None
     if not args.no_sweep:
-        opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=1e-3, tol_pri=1e-3,
-                             tol_dual=1e-3, rho0=rho0, w0_bot=cases.W0_BOT, alpha=args.alpha)
-        t1 = time.perf_counter()
-        out = ladmm.solve_batch(dc, w, opts=opts)
-        sweep = dict(plans=k, seconds=round(time.perf_counter() - t1, 4), tol_gap=1e-3, alpha=args.alpha,
-                     converged=int(np.sum(out["plan_status"] == ladmm.PLAN_CONVERGED)),
-                     max_iters=int(out["iters"].max()), median_iters=float(np.median(out["iters"])),
-                     max_rel_gap=float(out["rel_gap"].max()), passes=1)
+        # every plan to a certified gap <= tol_cert (objective provably within
+        # tol_cert of F*) with plain gap <= tol_cert and residuals <= 1e-4
+        opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=args.tol_cert, tol_pri=1e-4,
+                             tol_dual=1e-4, tol_cert=args.tol_cert, rho0=rho0,
+                             w0_bot=cases.W0_BOT, alpha=args.alpha)
+        sweeps = {"pass1": sweep(dc, w, opts, f"{precision}, pass 1")}
+        gpu_plan_iterations = sweeps["pass1"]["plan_iterations"]
+        sweeps["pass1"]["paper_budget_2x3000_seconds"] = round(2 * 3000 * k / value, 2)
         two = two_pass_sweep(ctx, case, w, precision, opts)
         if two:
-            sweep["two_pass"] = two
+            sweeps["two_pass"] = two
+        if not args.no_f64_sweep and precision != "f64":
+            dc.close()
+            d64 = ladmm.Case.from_case(ctx, case, "f64")
+            sweeps["f64_pass1"] = sweep(d64, w, opts, "plain FP64 GPU ADMM, pass 1")
+            sweeps["f64_pass1"]["speedup_of_" + precision] = round(
+                sweeps["f64_pass1"]["seconds"] / sweeps["pass1"]["seconds"], 2)
+            d64.close()
 
     if args.copy_probe:
         copy_probe()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, w, rho0, args.cpu_seconds)
+        cpu = cpu_baseline(case, w, rho0, args.cpu_seconds, gpu_plan_iterations)
 
     line = {
         "metric": "plan-iterations/s",
@@ -435,12 +550,13 @@ def main():
                                f"slider grid), {precision} dose block",
                    "points": N, "shots": n_t, "plans": k,
                    "iterations_per_step": ITERS_PER_STEP, "setup_ms": round(setup_ms, 2),
+                   "case_build_s": round(case_s, 1),
                    "tiles": {"gemm1": tiles[0], "gemm2": tiles[1]}},
         "launch": dict(mode=args.launch, plan_iterations_per_s=launch_modes),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
-        "sweep_1e-3": sweep,
+        "sweeps": sweeps,
         "last_check": {"max_rel_gap": float(np.max(res["rel_gap"])),
                        "max_r_pri": float(np.max(res["r_pri"]))},
     }

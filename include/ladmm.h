@@ -60,8 +60,24 @@ typedef enum {
  *                 A_hi B_hi + A_hi B_lo + A_lo B_hi on the BF16 MFMA with FP32
  *                 accumulation (about 2^-16 relative per product); iterates FP32.
  *                 The dose block takes 8 bytes per entry (two pairs, one per
- *                 product layout). */
-typedef enum { LADMM_F64 = 0, LADMM_F32 = 1, LADMM_BF16X3 = 2 } ladmm_precision;
+ *                 product layout).
+ *   LADMM_BF16:   BF16 dose block with iterative refinement of the x-update
+ *                 (the FP32-iteration / FP64-factor split of Sec. 3.A carried
+ *                 one step further).  Every iteration but the last of each check
+ *                 chunk reads the dose block once per product as a single BF16
+ *                 operand (2 bytes per entry; the rows of A are scaled to unit
+ *                 norm by E, Sec. 3.C, which is the per-column scale of the BF16
+ *                 block) and multiplies it, on the BF16 MFMA with FP32
+ *                 accumulation, by the change of the plan-side operand since the
+ *                 last refresh: A_s W = G_ref + D_hi' bf16(W - W_ref) and
+ *                 A_s' v = X_ref + D_hi bf16(v - v_ref).  The last iteration of
+ *                 every chunk is a refresh: three-term pair products (as
+ *                 LADMM_BF16X3) that also record G_ref, W_ref, X_ref, v_ref; the
+ *                 check statistics and the objective come from it.  The rounding
+ *                 then acts on the change alone, so the iterates converge to the
+ *                 fixed point of the exact products.  Iterates FP32; the low half
+ *                 of the dose block is read by the refresh only. */
+typedef enum { LADMM_F64 = 0, LADMM_F32 = 1, LADMM_BF16X3 = 2, LADMM_BF16 = 3 } ladmm_precision;
 
 /* Dose-point group types (App. A subscripts TS, TI, R, LD, O). */
 typedef enum { LADMM_PT_TS = 0, LADMM_PT_TI = 1, LADMM_PT_RING = 2, LADMM_PT_LD = 3,
@@ -107,8 +123,10 @@ typedef struct { double w_t, w_r, w_ld, w_bot; } ladmm_weights;
 
 /* Solver options.  Step size per plan: rho_j = rho0 * sqrt(w0_bot / w_BOT,j)
  * (Eq. rho_rule).  Plan j stops at the first check (every check_every
- * iterations) where rel_gap <= tol_gap, r_pri <= tol_pri and r_dual <= tol_dual;
- * tol_gap <= 0 runs exactly max_iter iterations (the fixed budget of Sec. 3.D). */
+ * iterations) where rel_gap <= tol_gap, r_pri <= tol_pri and r_dual <= tol_dual
+ * (and cert_gap <= tol_cert when tol_cert > 0; a tolerance <= 0 other than
+ * tol_gap is not used); tol_gap <= 0 and tol_cert <= 0 run exactly max_iter
+ * iterations (the fixed budget of Sec. 3.D). */
 typedef struct {
   int32_t max_iter;
   int32_t check_every;
@@ -131,6 +149,13 @@ typedef struct {
    * copies before the step; the residuals keep x.  alpha in (0, 2); 0 means 1.
    * Batches and solves only: ladmm_submit rejects alpha other than 0 or 1. */
   double alpha;
+  /* Stopping on the certified gap (see ladmm_result.cert_gap): with tol_cert
+   * > 0 a plan also needs cert_gap <= tol_cert to stop, which proves its
+   * objective within tol_cert (relative) of the exact optimum F*.  0: not used.
+   * A plan stops at the first check where every tolerance in use holds
+   * (tol_gap, tol_cert, and tol_pri, tol_dual when > 0); with tol_gap <= 0 and
+   * tol_cert <= 0 it runs exactly max_iter iterations. */
+  double tol_cert;
 } ladmm_opts;
 
 /* Per-plan results; every pointer is caller-owned host memory or NULL.
@@ -138,12 +163,23 @@ typedef struct {
  *   bot      : k x n_iso  tau_i = (phi_cal/D_T) max_s sum_c t_isc
  *   objective: F_j(t), the planning objective (hinge terms + w_BOT sum tau)
  *   dual_obj : c'z1, the dual-LP objective at the box-feasible copy
- *   rel_gap  : |F + c'z1| / max(F, 1e-300)
+ *   rel_gap  : |F + c'z1| / max(F, 1e-300) (the plain gap: not a bound)
  *   r_pri    : ||x - z|| / max(||x||, ||z||);  r_dual: ||z - z_prev|| / ||y||
- *   iters    : iterations run;  plan_status: ladmm_plan_status */
+ *   iters    : iterations run;  plan_status: ladmm_plan_status
+ *   lower_bound: L <= F* by LP duality (App. A): x = (clip(z1, 0, u), sector
+ *              values as small as the shot rows allow), scaled by the largest
+ *              theta <= 1 that keeps every BOT row within w_BOT, is feasible
+ *              for the dual LP, so L = -c'x <= -p* = F*.
+ *   cert_gap : (U - L) / U with U an upper bound on F(t~) >= F* for the
+ *              OAR-feasible shot times t~ = t / max(1, max_O d_O / D_O):
+ *              U = F(t) + (1 - 1/r) sum_targets u d / D when the OAR ratio r
+ *              exceeds 1.  Certifies |F(t~) - F*| <= cert_gap * U.
+ * lower_bound and cert_gap are evaluated in the iteration precision of the
+ * products (FP64 sums); the certificate is as rigorous as those products. */
 typedef struct {
   double *t, *bot, *objective, *dual_obj, *rel_gap, *r_pri, *r_dual;
   int32_t *iters, *plan_status;
+  double *lower_bound, *cert_gap;
 } ladmm_result;
 
 typedef struct ladmm_ctx ladmm_ctx;
@@ -206,6 +242,10 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1,
 /* Device time of the iterations run so far, in milliseconds, and the number of
  * plan-iterations. */
 int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_iterations);
+/* Current step size rho_j of every plan (host, k values): the rule of
+ * Eq. rho_rule at the start, changed by step-size balancing when adapt_rho is
+ * on.  The exported scaled duals y are the multipliers divided by these. */
+int ladmm_batch_step_sizes(const ladmm_batch *b, double *rho);
 
 /* Per-kernel timing.  With profiling on, every kernel launch of an iteration
  * is bracketed by HIP events recorded on the batch's stream; the elapsed times
@@ -213,8 +253,11 @@ int ladmm_batch_timing(const ladmm_batch *b, double *iterate_ms, int64_t *plan_i
  * 0 GEMM1 (A_s W, the dose-point part of the right-hand side), 1 rhs assembly,
  * 2 S^-1 product, 3 post (small-side update), 4 GEMM2 (closed-form x-step with
  * the fused z- and y-steps), 5 objective product, 6 shot-time scaling,
- * 7 finalize.  ms_total and launches are arrays of LADMM_N_KERNEL_CLASSES. */
-#define LADMM_N_KERNEL_CLASSES 8
+ * 7 finalize, 8 certificate (z1, its product with the dose block, the sector
+ * values of the dual point), 9 GEMM1 and 10 GEMM2 of a refresh iteration of
+ * LADMM_BF16 (its other iterations count under 0 and 4).  ms_total and
+ * launches are arrays of LADMM_N_KERNEL_CLASSES. */
+#define LADMM_N_KERNEL_CLASSES 11
 /* Tile configurations chosen for the two dose-matrix products of a batch.
  * Before its first iteration a batch times every tile configuration of the
  * products on its own data and keeps the fastest (cached per case and padded

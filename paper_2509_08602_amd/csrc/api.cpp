@@ -179,7 +179,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
     return fail(LADMM_E_INVALID, "dose, point_group and groups are required");
   if (!(d->prescription_mean > 0) || !(d->phi_cal > 0))
     return fail(LADMM_E_INVALID, "prescription_mean and phi_cal must be > 0");
-  if (d->precision != LADMM_F64 && d->precision != LADMM_F32 && d->precision != LADMM_BF16X3)
+  if (d->precision != LADMM_F64 && d->precision != LADMM_F32 && !bf16_block(d->precision))
     return fail(LADMM_E_INVALID, "unknown precision");
   const int n_t = d->n_iso * d->n_sectors * d->n_collimators;
   for (int g = 0; g < d->n_groups; ++g) {
@@ -634,6 +634,22 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->v = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->vT = p;
   B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * Tsz)); b->that = p;
+  if (c->precision == LADMM_BF16) {
+    // references of the refinement (zero: the first products are of the full operands)
+    B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * sizeof(float))); b->xref = (float *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * sizeof(float))); b->wref = (float *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * sizeof(double))); b->gref = (double *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * sizeof(double))); b->vref = (double *)p;
+    B_RC(batch_alloc(b, &p, (size_t)kp * c->Np * sizeof(uint16_t))); b->dW = (uint16_t *)p;
+    B_HIP(hipMemsetAsync(b->xref, 0, (size_t)c->Np * kp * sizeof(float), b->stream));
+    B_HIP(hipMemsetAsync(b->wref, 0, (size_t)c->Np * kp * sizeof(float), b->stream));
+    B_HIP(hipMemsetAsync(b->gref, 0, (size_t)c->ntp * kp * sizeof(double), b->stream));
+    B_HIP(hipMemsetAsync(b->vref, 0, (size_t)c->ntp * kp * sizeof(double), b->stream));
+    B_HIP(hipMemsetAsync(b->dW, 0, (size_t)kp * c->Np * sizeof(uint16_t), b->stream));
+  }
+  // certificate operand (z1 of the points) and sector values
+  B_RC(batch_alloc(b, &p, (size_t)c->Np * kp * Tsz)); b->zc = p;
+  B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * sizeof(double))); b->need = (double *)p;
   // statistics partials: one per row block of GEMM2, sized for the smallest
   // row block of any tile configuration (the autotuner may pick it)
   const int max_row_blocks = c->Np / kNnStatRows;
@@ -725,6 +741,12 @@ int iterate_once(ladmm_batch *b, bool stats) {
     eo.stats = b->obj_stats;
     PROF(5, (gemm_nn<T>(s, EPI_OBJ, (const T *)c->D, c->ntp, (const T *)b->that, kp, c->Np, kp,
                         c->ntp, eo, b->cfg2)));
+    // certificate: z1 of the new iterate times the dose block (the GEMM1
+    // partials are free until the next iteration)
+    PROF(8, (z_from_q<T>(s, (const T *)b->q, (T *)b->zc, c->Np, kp, pt)));
+    PROF(8, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->zc, kp, (T *)b->P1, kp, c->ntp,
+                        kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
+    PROF(8, (cert_need<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->need)));
     FinalArgs fa;
     fa.admm_stats = b->admm_stats;
     fa.admm_blocks = b->admm_blocks;
@@ -739,6 +761,7 @@ int iterate_once(ladmm_batch *b, bool stats) {
     fa.L = c->L;
     fa.cs = c->cs;
     fa.kp = kp;
+    fa.need = b->need;
     fa.out = b->fin;
     PROF(7, (finalize(s, fa)));
   }
@@ -750,6 +773,45 @@ int iterate_once(ladmm_batch *b, bool stats) {
 BfPair plan_pairs(void *buf, int kp, int len) {
   const uint16_t *h = (const uint16_t *)buf;
   return BfPair{h, h + (size_t)kp * len, len};
+}
+
+// The check after a pair-product iteration: the objective product of the
+// current shot times (pairs) and the per-plan statistics.
+int check_stats_bf(ladmm_batch *b, const EpiArgs<float> &ea) {
+  ladmm_case *c = b->c;
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  const BfPair Dp{c->Dh, c->Dl, c->ntp};
+  SmallArgs sa = small_args(b);
+  const BfPair Tt = plan_pairs(b->that, kp, c->ntp);
+  PROF(6, (shot_scaled_bf(s, sa, b->q2, (uint16_t *)Tt.hi, (uint16_t *)Tt.lo)));
+  EpiArgs<float> eo = ea;
+  eo.stats = b->obj_stats;
+  PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, b->cfg2)));
+  // certificate: z1 of the new iterate (pairs) times the dose block
+  const BfPair DT{c->DTh, c->DTl, c->Np};
+  const BfPair Z = plan_pairs(b->zc, kp, c->Np);
+  PROF(8, (z_from_q_bf(s, (const float *)b->q, c->Np, kp, ea.pt, (uint16_t *)Z.hi, (uint16_t *)Z.lo)));
+  PROF(8, (gemm_bf_tn(s, DT, Z, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+  PROF(8, (cert_need<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->need)));
+  FinalArgs fa;
+  fa.admm_stats = b->admm_stats;
+  fa.admm_blocks = b->admm_blocks;
+  fa.post_stats = b->post_stats;
+  fa.post_blocks = b->post_blocks;
+  fa.obj_stats = b->obj_stats;
+  fa.obj_blocks = b->obj_blocks;
+  fa.q2 = b->q2;
+  fa.E = c->E;
+  fa.invrho = b->invrho;
+  fa.wbot = b->wbot;
+  fa.L = c->L;
+  fa.cs = c->cs;
+  fa.kp = kp;
+  fa.need = b->need;
+  fa.out = b->fin;
+  PROF(7, (finalize(s, fa)));
+  return LADMM_OK;
 }
 
 // One iteration with the BF16-pair products (same steps as iterate_once).
@@ -780,36 +842,67 @@ int iterate_bf(ladmm_batch *b, bool stats) {
   ea.ldwt = c->Np;
   ea.alpha = b->alpha;
   PROF(4, (gemm_bf_nn(s, stats ? EPI_ADMM_STATS : EPI_ADMM, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2)));
-  if (stats) {
-    const BfPair Tt = plan_pairs(b->that, kp, c->ntp);
-    PROF(6, (shot_scaled_bf(s, sa, b->q2, (uint16_t *)Tt.hi, (uint16_t *)Tt.lo)));
-    EpiArgs<float> eo = ea;
-    eo.stats = b->obj_stats;
-    PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, b->cfg2)));
-    FinalArgs fa;
-    fa.admm_stats = b->admm_stats;
-    fa.admm_blocks = b->admm_blocks;
-    fa.post_stats = b->post_stats;
-    fa.post_blocks = b->post_blocks;
-    fa.obj_stats = b->obj_stats;
-    fa.obj_blocks = b->obj_blocks;
-    fa.q2 = b->q2;
-    fa.E = c->E;
-    fa.invrho = b->invrho;
-    fa.wbot = b->wbot;
-    fa.L = c->L;
-    fa.cs = c->cs;
-    fa.kp = kp;
-    fa.out = b->fin;
-    PROF(7, (finalize(s, fa)));
-  }
+  if (stats) return check_stats_bf(b, ea);
   return LADMM_OK;
 }
 
-int iterate_any(ladmm_batch *b, bool stats) {
+// One iteration of the refinement mode (LADMM_BF16).  phase BF_DELTA: single
+int iterate_bfr(ladmm_batch *b, int phase) {
+  ladmm_case *c = b->c;
+  if (phase == BF_PLAIN) return iterate_bf(b, false);
+  hipStream_t s = b->stream;
+  const int kp = b->kp;
+  const bool refresh = phase == BF_REFRESH;
+  const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
+  const BfPair W = plan_pairs(b->W, kp, c->Np), V = plan_pairs(b->vT, kp, c->ntp);
+  const BfPair dW{b->dW, nullptr, c->Np}, dV{V.hi, nullptr, c->ntp};
+  SmallArgs sa = small_args(b);
+  if (refresh)
+    PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+  else
+    PROF(0, (gemm_bf_tn(s, DT, dW, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 1, b->cfg1)));
+  PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r,
+                      refresh ? nullptr : b->gref, refresh ? b->gref : nullptr)));
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+                           c->nchunk2, nullptr, b->cfg_s)));
+  if (refresh)
+    PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
+                        (uint16_t *)V.lo, b->vref)));
+  else
+    PROF(3, (vreduce_delta_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, b->vref,
+                              (uint16_t *)V.hi)));
+  PROF(3, (post(s, sa, b->v, b->qs, b->q2, refresh ? b->post_stats : nullptr, &b->post_blocks)));
+  EpiArgs<float> ea{};
+  ea.q = (float *)b->q;
+  ea.ldq = kp;
+  ea.invrho = b->invrho;
+  ea.active = b->active;
+  ea.stats = b->admm_stats;
+  ea.nstat_cols = kp;
+  ea.pt = point_table<float>(b);
+  ea.wt_hi = (uint16_t *)W.hi;
+  ea.wt_lo = (uint16_t *)W.lo;
+  ea.ldwt = c->Np;
+  ea.alpha = b->alpha;
+  ea.xref = b->xref;
+  ea.wref = b->wref;
+  ea.dw = b->dW;
+  if (refresh)
+    PROF(10, (gemm_bf_nn(s, EPI_ADMM_STATS, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2, BF_REFRESH)));
+  else
+    PROF(4, (gemm_bf_nn(s, EPI_ADMM, Dp, dV, c->Np, kp, c->ntp, ea, 1, b->cfg2, phase)));
+  if (refresh) return check_stats_bf(b, ea);
+  return LADMM_OK;
+}
+
+// Iteration i of a chunk of n (the last one with statistics).
+int iterate_any(ladmm_batch *b, int i, int n) {
+  const bool stats = i == n - 1;
   switch (b->c->precision) {
     case LADMM_F64: return iterate_once<double>(b, stats);
     case LADMM_F32: return iterate_once<float>(b, stats);
+    case LADMM_BF16:
+      return iterate_bfr(b, stats ? BF_REFRESH : i == n - 2 ? BF_DELTA_PAIR : BF_DELTA);
     default: return iterate_bf(b, stats);
   }
 }
@@ -826,7 +919,7 @@ void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np 
 // point-row (which = 1) product of this batch's shapes.
 bool cfg_ok(const ladmm_batch *b, int which, int cfg) {
   const ladmm_case *c = b->c;
-  if (c->precision == LADMM_BF16X3)
+  if (bf16_block(c->precision))
     return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kp) : gemm_bf_cfg_ok(1, cfg, c->Np, b->kp);
   return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kp) : gemm_nn_cfg_ok(cfg, c->Np, b->kp);
 }
@@ -838,11 +931,13 @@ hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact)
   ladmm_case *c = b->c;
   hipStream_t s = b->stream;
   const int kp = b->kp;
-  if (c->precision == LADMM_BF16X3) {
+  if (bf16_block(c->precision)) {
+    // LADMM_BF16 times its hot iterations: single-operand products
+    const bool one = c->precision == LADMM_BF16;
     const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
     if (which == 0)
-      return gemm_bf_tn(s, DT, plan_pairs(b->W, kp, c->Np), (float *)b->P1, kp, c->ntp, kp, c->Np,
-                        c->nchunk1, 3, cfg);
+      return gemm_bf_tn(s, DT, one ? BfPair{b->dW, nullptr, c->Np} : plan_pairs(b->W, kp, c->Np),
+                        (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, one ? 1 : 3, cfg);
     EpiArgs<float> ea{};
     ea.q = (float *)b->q;
     ea.ldq = kp;
@@ -853,7 +948,12 @@ hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact)
     ea.wt_lo = (uint16_t *)b->W + (size_t)kp * c->Np;
     ea.ldwt = c->Np;
     ea.alpha = b->alpha;
-    return gemm_bf_nn(s, EPI_ADMM, Dp, plan_pairs(b->vT, kp, c->ntp), c->Np, kp, c->ntp, ea, 3, cfg);
+    ea.xref = b->xref;
+    ea.wref = b->wref;
+    ea.dw = b->dW;
+    const BfPair V = plan_pairs(b->vT, kp, c->ntp);
+    return gemm_bf_nn(s, EPI_ADMM, Dp, one ? BfPair{V.hi, nullptr, c->ntp} : V, c->Np, kp, c->ntp, ea,
+                      one ? 1 : 3, cfg, one ? BF_DELTA : BF_PLAIN);
   }
   if (which == 0)
     return gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1, kp, c->ntp, kp,
@@ -954,7 +1054,7 @@ int prepare_batch(ladmm_batch *b) {
 int enqueue_iterations(ladmm_batch *b, int n) {
   if (b->profiling || !b->graphs) {
     for (int i = 0; i < n; ++i) {
-      int rc = iterate_any(b, i == n - 1);
+      int rc = iterate_any(b, i, n);
       if (rc) return rc;
     }
     return LADMM_OK;
@@ -973,7 +1073,7 @@ int enqueue_iterations(ladmm_batch *b, int n) {
       return fail(LADMM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     }
     int rc = LADMM_OK;
-    for (int i = 0; i < n && rc == LADMM_OK; ++i) rc = iterate_any(b, i == n - 1);
+    for (int i = 0; i < n && rc == LADMM_OK; ++i) rc = iterate_any(b, i, n);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->stream, &graph);
     b->stream = run_stream;
@@ -1027,7 +1127,7 @@ int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed_out) {
     std::memcpy(&b->rec[(size_t)j * kFinal], f, kFinal * sizeof(double));
     b->iters[j] = b->iters_run - b->start[j];
     bool bad = false;
-    for (int q = 0; q < kFinal; ++q) bad |= !std::isfinite(f[q]);
+    for (int q = 0; q < 8; ++q) bad |= !std::isfinite(f[q]);   // the certificate may be undefined
     if (bad) {
       b->status[j] = LADMM_PLAN_NUMERIC;
       b->h_active[j] = 0;
@@ -1036,7 +1136,7 @@ int chunk_complete(ladmm_batch *b, int n, bool decide, bool *changed_out) {
     }
     if (!decide) continue;
     const StopRule &r = b->rule[j];
-    if (r.tol_gap > 0 && f[2] <= r.tol_gap && f[3] <= r.tol_pri && f[4] <= r.tol_dual) {
+    if (rule_met(r, f)) {
       b->status[j] = LADMM_PLAN_CONVERGED;
       b->h_active[j] = 0;
       changed = true;
@@ -1082,7 +1182,7 @@ int adapt_rho(ladmm_batch *b, bool *switched) {
       HIPC(w_from_q<float>(s, (const float *)b->q, (float *)b->W, c->Np, b->kp, point_table<float>(b)));
     else
       HIPC(w_from_q_bf(s, (const float *)b->q, c->Np, b->kp, point_table<float>(b), (uint16_t *)b->W,
-                       (uint16_t *)b->W + (size_t)b->kp * c->Np));
+                       (uint16_t *)b->W + (size_t)b->kp * c->Np, b->wref, b->dW));
   }
   return LADMM_OK;
 }
@@ -1164,6 +1264,8 @@ int results_impl(ladmm_batch *b, ladmm_result *out) {
     if (out->r_dual) out->r_dual[j] = f[4];
     if (out->iters) out->iters[j] = b->iters[j];
     if (out->plan_status) out->plan_status[j] = b->status[j];
+    if (out->lower_bound) out->lower_bound[j] = f[8];
+    if (out->cert_gap) out->cert_gap[j] = f[9];
   }
   return LADMM_OK;
 }
@@ -1356,7 +1458,7 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const
                             point_table<float>(b));
       else if (e == hipSuccess)
         e = w_from_q_bf(b->stream, (const float *)b->q, c->Np, kp, point_table<float>(b),
-                        (uint16_t *)b->W, (uint16_t *)b->W + (size_t)kp * c->Np);
+                        (uint16_t *)b->W, (uint16_t *)b->W + (size_t)kp * c->Np, b->wref, b->dW);
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1398,6 +1500,13 @@ int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *la
     if (ms_total) ms_total[i] = b->kms[i];
     if (launches) launches[i] = b->kcount[i];
   }
+  return LADMM_OK;
+}
+
+int ladmm_batch_step_sizes(const ladmm_batch *b, double *rho) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (!rho) return fail(LADMM_E_INVALID, "null rho");
+  for (int j = 0; j < b->k; ++j) rho[j] = b->rho[j];
   return LADMM_OK;
 }
 

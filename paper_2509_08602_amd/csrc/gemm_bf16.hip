@@ -1,4 +1,5 @@
-// BF16-pair MFMA products for the large case (precision mode LADMM_BF16X3).
+// BF16 MFMA products for the large case (precision modes LADMM_BF16X3 and
+// LADMM_BF16).
 //
 // The dose block D^ and the plan-side operands (W = z1 - y1, v_top, the scaled
 // shot times) are carried as pairs hi = bf16(x), lo = bf16(x - hi), which keep
@@ -7,6 +8,18 @@
 // term is below 2^-16 relative.  This is the split-BF16 product that carries the
 // x-update of Eq. (partial_elimination) at close to FP32 accuracy on the BF16
 // matrix cores; the Schur complement solve and the small side stay FP64.
+//
+// LADMM_BF16 reads the dose block as a single BF16 operand (the hi half) in
+// every hot iteration and multiplies it by the change of the plan-side operand
+// since the last refresh, dW = bf16(W - W_ref) and dv = bf16(v - v_ref):
+//   A_s W = G_ref + D_hi' dW,   A_s' v = X_ref + D_hi dv,
+// where G_ref = D^' W_ref and X_ref = D^ v_ref are three-term (near FP32)
+// products taken at the last refresh.  The BF16 rounding of the dose block and
+// of the operand then acts only on the change, which shrinks as the iterates
+// converge, so the fixed point is that of the exact products: this is the
+// iterative refinement of the x-update of Eq. (partial_elimination).  The
+// refresh is the last iteration of every check chunk, so the statistics and
+// the objective of every check come from the three-term products.
 //
 // MFMA 16x16x32 bf16 operand layout (gfx950, checked by a lane probe): lane l
 // supplies A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and
@@ -46,6 +59,15 @@ __device__ __forceinline__ void split_pair(double x, uint16_t &h, uint16_t &l) {
   l = bf_bits((__bf16)(float)r);
 }
 
+__device__ __forceinline__ float bf_val(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// The value a pair carries: hi + lo is exact in FP32 (17 significant bits at most).
+__device__ __forceinline__ float pair_val(uint16_t h, uint16_t l) { return bf_val(h) + bf_val(l); }
+
+__device__ __forceinline__ uint16_t bf_round(float x) { return bf_bits((__bf16)x); }
+
 __device__ __forceinline__ float clip0u_f(float q, float u) { return fminf(fmaxf(q, 0.f), u); }
 
 // Consecutive tile indices on one XCD (workgroups go round-robin over the 8
@@ -82,32 +104,42 @@ constexpr int bf_nstat() { return MODE == EPI_OBJ ? kObjStats : kAdmmStats; }
 template <int MODE>
 constexpr bool bf_has_stats() { return MODE == EPI_ADMM_STATS || MODE == EPI_OBJ; }
 // LDS of the epilogue: the statistics partials (one per 16-row tile, statistic
-// and column); in the plain ADMM epilogue, W' hi and lo halves staged as BN
-// columns of BM rows (padded by 8 elements, 16-byte aligned columns) so that
-// each plan's rows leave as contiguous 16-byte pieces.  The statistics variant
-// (one launch per convergence check) stores W' directly instead: staging on top
-// of its partials would halve its occupancy.
+// and column); in the plain ADMM epilogue, W' hi and lo halves (or dW alone in
+// the BF_DELTA variant) staged as BN columns of BM rows (padded by 8 elements,
+// 16-byte aligned columns) so that each plan's rows leave as contiguous
+// 16-byte pieces.  The statistics variant (one launch per convergence check)
+// stores its plan-major outputs directly instead: staging on top of its
+// partials would halve its occupancy.
 template <int BM, int BN, int MODE>
 constexpr size_t bf_stat_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
 template <int BM>
 constexpr int bf_wstage_ld() { return BM + 8; }
 template <int MODE>
 constexpr bool bf_wstaged() { return MODE == EPI_ADMM; }
-template <int BM, int BN, int MODE>
+template <int DL>
+constexpr int bf_wstage_halves() { return DL == BF_DELTA ? 1 : 2; }
+template <int BM, int BN, int MODE, int DL>
 constexpr size_t bf_red_bytes() {
-  return bf_stat_bytes<BM, BN, MODE>() + (bf_wstaged<MODE>() ? 2 * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
+  return bf_stat_bytes<BM, BN, MODE>() +
+         (bf_wstaged<MODE>() ? bf_wstage_halves<DL>() * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
 }
 
 __device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
 
+__device__ __forceinline__ uint2 pack4(const uint16_t (&v)[4]) {
+  return uint2{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16)};
+}
+
 // After the k loop, shared by both kernels.  MODE 0: the split-K partial
 // store; otherwise the point-row epilogue EPI_ADMM / _STATS / _OBJ with the
-// same arithmetic as the FP32 path and W' written plan-major as pairs.
+// same arithmetic as the FP32 path and W' written plan-major.  DL selects the
+// variant of the BF16 refinement mode (BF_PLAIN for the pair mode and the
+// objective product).
 // Statistics: per 16-row tile, every lane sums its 4 rows, two shuffles combine
 // the 4 lanes of a column, and the two tiles of each 32-row block are added
 // (one partial per 32-row block).  `smem` must hold bf_red_bytes and no wave
 // may still read operand tiles from it.
-template <int BM, int BN, int WM, int WN, int MODE>
+template <int BM, int BN, int WM, int WN, int MODE, int DL>
 __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 * WN)],
                                             unsigned char *smem, int tid, int mt, int m0, int n0,
                                             int zc, float *__restrict__ P, int ldp, size_t pstride,
@@ -116,6 +148,13 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
   constexpr int TM = BM / (16 * WM), TN = BN / (16 * WN);
   constexpr int NST = bf_nstat<MODE>();
   constexpr bool kStats = bf_has_stats<MODE>();
+  constexpr bool kDeltaIn = DL == BF_DELTA || DL == BF_DELTA_PAIR;   // product = X_ref + D_hi dv
+  constexpr bool kPairsOut = DL != BF_DELTA;                          // W' as pairs
+  constexpr bool kDwOut = DL == BF_DELTA || DL == BF_REFRESH;         // dW = bf16(W' - W_ref)
+  static_assert(MODE != EPI_OBJ || DL == BF_PLAIN, "the objective product has no refinement variant");
+  static_assert(DL != BF_REFRESH || !bf_wstaged<MODE>(), "the refresh stores its outputs directly");
+  static_assert(MODE != EPI_ADMM_STATS || DL == BF_PLAIN || DL == BF_REFRESH,
+                "statistics come from the pair products");
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   if (MODE == 0) {
@@ -165,11 +204,16 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
       double st[NST];
 #pragma unroll
       for (int q = 0; q < NST; ++q) st[q] = 0.0;
-      uint16_t wh[4] = {0, 0, 0, 0}, wl[4] = {0, 0, 0, 0};
-      float qv4[4];
+      uint16_t wh[4] = {0, 0, 0, 0}, wl[4] = {0, 0, 0, 0}, dw[4] = {0, 0, 0, 0};
+      float qv4[4], xr4[4], wr4[4];
       if (MODE != EPI_OBJ) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) qv4[r] = ea.q[(size_t)(mb + r) * ea.ldq + n];
+        for (int r = 0; r < 4; ++r) {
+          const size_t o = (size_t)(mb + r) * ea.ldq + n;
+          qv4[r] = ea.q[o];
+          if (kDeltaIn) xr4[r] = ea.xref[o];
+          if (DL == BF_DELTA) wr4[r] = ea.wref[o];
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -177,22 +221,37 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
         const int g = grow[tm][r];
         const float sg = srow[tm][r];
         const float u = upper_bf(ea.pt, g, m, n);
-        const float s = acc[tm][tn][r];
+        float s = acc[tm][tn][r];
+        if (kDeltaIn) s = xr4[r] + s;
         if (MODE == EPI_OBJ) {
           if (ea.pt.is_oar[g]) {
             st[1] = fmax(st[1], (double)(-s));
           } else {
             const double h = fmax(0.0, (double)sg - (double)s);
             st[0] = fma((double)u, h, st[0]);
+            if (sg > 0.f) st[2] = fma((double)u, (double)s, st[2]);
           }
         } else {
           const float qv = qv4[r];
           const float z = clip0u_f(qv, u);
+          float wref = 0.f;
+          if (DL == BF_DELTA) wref = wr4[r];
+          if (DL == BF_REFRESH) {
+            // the references of every column (frozen ones too: they stay
+            // consistent with q, which the refresh leaves unchanged there)
+            uint16_t h, l;
+            split_pair((double)(2.f * z - qv), h, l);   // the pairs the refresh's GEMM1 read
+            wref = pair_val(h, l);
+            const size_t o = (size_t)m * ea.ldq + n;
+            ea.xref[o] = s;
+            ea.wref[o] = wref;
+          }
           const float qx = z + sg * irc[tn] - s;   // x + y of the closed-form x-step
           // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
           const float qn = ea.alpha == 1.0 ? qx : qv + (float)ea.alpha * (qx - qv);
           const float wv = 2.f * clip0u_f(qn, u) - qn;
-          split_pair((double)wv, wh[r], wl[r]);
+          if (kPairsOut) split_pair((double)wv, wh[r], wl[r]);
+          if (kDwOut) dw[r] = bf_round(wv - wref);
           if (act[tn]) ea.q[(size_t)m * ea.ldq + n] = qn;
           if (MODE == EPI_ADMM_STATS) {
             const double yo = (double)qv - (double)z;
@@ -213,16 +272,17 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
       if (bf_wstaged<MODE>()) {
         // staged: column n - n0, rows mb - m0 .. + 3
         const int cl = n - n0, rl = mb - m0;
-        *reinterpret_cast<uint2 *>(&swh[cl][rl]) =
-            uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
-        *reinterpret_cast<uint2 *>(&swl[cl][rl]) =
-            uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
+        if (DL == BF_DELTA) {
+          *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(dw);
+        } else {
+          *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(wh);
+          *reinterpret_cast<uint2 *>(&swl[cl][rl]) = pack4(wl);
+        }
       } else if (MODE == EPI_ADMM_STATS && act[tn]) {
         const size_t o = (size_t)n * ea.ldwt + mb;
-        *reinterpret_cast<uint2 *>(ea.wt_hi + o) =
-            uint2{(uint32_t)wh[0] | ((uint32_t)wh[1] << 16), (uint32_t)wh[2] | ((uint32_t)wh[3] << 16)};
-        *reinterpret_cast<uint2 *>(ea.wt_lo + o) =
-            uint2{(uint32_t)wl[0] | ((uint32_t)wl[1] << 16), (uint32_t)wl[2] | ((uint32_t)wl[3] << 16)};
+        *reinterpret_cast<uint2 *>(ea.wt_hi + o) = pack4(wh);
+        *reinterpret_cast<uint2 *>(ea.wt_lo + o) = pack4(wl);
+        if (kDwOut) *reinterpret_cast<uint2 *>(ea.dw + o) = pack4(dw);
       }
       if (kStats) {
 #pragma unroll
@@ -242,14 +302,18 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
   if (MODE == EPI_OBJ && !kStats) return;
   __syncthreads();
   if (bf_wstaged<MODE>()) {
-    // W' of the active plans: each column's BM rows as 16-byte pieces, in order
+    // W' (or dW) of the active plans: each column's BM rows as 16-byte pieces, in order
     for (int e = tid; e < BN * (BM / 8); e += NT) {
       const int cl = e / (BM / 8), ch = (e % (BM / 8)) * 8;
       const int n = n0 + cl;
       if (!ea.active[n]) continue;
       const size_t o = (size_t)n * ea.ldwt + m0 + ch;
-      *reinterpret_cast<uint4 *>(ea.wt_hi + o) = *reinterpret_cast<const uint4 *>(&swh[cl][ch]);
-      *reinterpret_cast<uint4 *>(ea.wt_lo + o) = *reinterpret_cast<const uint4 *>(&swl[cl][ch]);
+      if (DL == BF_DELTA) {
+        *reinterpret_cast<uint4 *>(ea.dw + o) = *reinterpret_cast<const uint4 *>(&swh[cl][ch]);
+      } else {
+        *reinterpret_cast<uint4 *>(ea.wt_hi + o) = *reinterpret_cast<const uint4 *>(&swh[cl][ch]);
+        *reinterpret_cast<uint4 *>(ea.wt_lo + o) = *reinterpret_cast<const uint4 *>(&swl[cl][ch]);
+      }
     }
   }
   if (!kStats) return;
@@ -265,7 +329,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
 // the NN epilogue.  NBUF: 2 = double-buffered LDS stages; 1 = one stage (half
 // the LDS, so more workgroups per CU), the next stage waiting in registers
 // behind a barrier.
-template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF>
+template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF, int DL>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, int K, int kchunk,
                                                          int mtiles, int ntiles,
                                                          float *__restrict__ P, int ldp,
@@ -277,11 +341,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
   constexpr int KV = kBfBK / 8;                        // 16-byte vectors per row slice
   constexpr int AV = BM * KV, BV = BN * KV;
   constexpr int AVT = (AV + NT - 1) / NT, BVT = (BV + NT - 1) / NT;
-  constexpr bool ALO = TERMS == 3;
+  static_assert(TERMS == 1 || TERMS == 3, "one or three products per k step");
+  constexpr bool ALO = TERMS == 3;   // A_lo B_hi and A_hi B_lo terms
   constexpr size_t kTileA = sizeof(uint16_t) * NBUF * BM * kBfLd;
   constexpr size_t kTileB = sizeof(uint16_t) * NBUF * BN * kBfLd;
-  constexpr size_t kBytesT = kTileA * (ALO ? 2 : 1) + kTileB * 2;
-  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE>();
+  constexpr size_t kBytesT = kTileA * (ALO ? 2 : 1) + kTileB * (ALO ? 2 : 1);
+  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE, DL>();
   constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   auto sAh = reinterpret_cast<uint16_t (*)[BM][kBfLd]>(smem);
@@ -309,7 +374,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
   static_assert(KV == 4, "one fragment per 16 rows and k step");
   auto a_row = [](int e) { return (e >> 6) * 16 + (e & 15); };
   auto a_kv = [](int e) { return ((e & 63) >> 4) * 8; };
-  uint4 rah[AVT], ral[ALO ? AVT : 1], rbh[BVT], rbl[BVT];
+  uint4 rah[AVT], ral[ALO ? AVT : 1], rbh[BVT], rbl[ALO ? BVT : 1];
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < AVT; ++i) {
@@ -328,7 +393,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
         const int row = e / KV, k = k0 + (e % KV) * 8;
         const size_t off = (size_t)(n0 + row) * B.ld + k;
         rbh[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
-        rbl[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
+        if (ALO) rbl[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
       }
     }
   };
@@ -347,7 +412,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
       if (e < BV) {
         const int row = e / KV, kv = (e % KV) * 8;
         *reinterpret_cast<uint4 *>(&sBh[buf][row][kv]) = rbh[i];
-        *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[i];
+        if (ALO) *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[i];
       }
     }
   };
@@ -361,7 +426,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
     for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
       const bool more = k0 + kBfBK < kend;
       if (more) load(k0 + kBfBK);
-      bf8v ah[TM], al[ALO ? TM : 1], bh[TN], bl[TN];
+      bf8v ah[TM], al[ALO ? TM : 1], bh[TN], bl[ALO ? TN : 1];
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm) {
         const int row = wm * TM * 16 + tm * 16 + r16;
@@ -372,17 +437,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
       for (int tn = 0; tn < TN; ++tn) {
         const int row = wn * TN * 16 + tn * 16 + r16;
         bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][row][g8]);
-        bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][row][g8]);
+        if (ALO) bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][row][g8]);
       }
       // term-major: TM TN independent products between two on one accumulator
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(ah[tm], bh[tn], acc[tm][tn]);
+      if (ALO) {
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
+        for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(ah[tm], bl[tn], acc[tm][tn]);
+          for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(ah[tm], bl[tn], acc[tm][tn]);
+      }
       if (ALO) {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
@@ -400,7 +467,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
       }
     }
   }
-  bf_epilogue<BM, BN, WM, WN, MODE>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+  bf_epilogue<BM, BN, WM, WN, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
 }
 
 // Direct-A variant.  The waves split the rows only, so the rows of A a wave
@@ -412,7 +479,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
 // same order as k_gemm_bf, so both kernels give the same bits.  LDS traffic per
 // k-step and wave: 2 TN fragment reads for 3 TM TN MFMAs, against 2 (TM + TN)
 // with A staged too.
-template <int TM, int TN, int WM, int PD, int TERMS, int MODE>
+template <int TM, int TN, int WM, int PD, int TERMS, int MODE, int DL>
 __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K, int kchunk,
                                                       int mtiles, int ntiles,
                                                       float *__restrict__ P, int ldp,
@@ -420,13 +487,15 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
   constexpr int BM = TM * 16 * WM, BN = TN * 16, NT = 64 * WM;
   constexpr int KV = kBfBK / 8;
   constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
-  constexpr bool ALO = TERMS == 3;
+  static_assert(TERMS == 1 || TERMS == 3, "one or three products per k step");
+  constexpr bool ALO = TERMS == 3;   // A_lo B_hi and A_hi B_lo terms
   constexpr int TA = ALO ? TM : 1;
+  constexpr int BVL = ALO ? BVT : 1;
   static_assert(PD >= 1, "prefetch distance");
   static_assert(MODE == 0 || (TM * 16) % 32 == 0, "statistics partials are per 32-row block");
   constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
-  constexpr size_t kBytesT = 2 * kTileB;
-  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE>();
+  constexpr size_t kBytesT = (ALO ? 2 : 1) * kTileB;
+  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE, DL>();
   constexpr size_t kBytes = kBytesT > kBytesR ? kBytesT : kBytesR;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   auto sBh = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem);
@@ -451,7 +520,7 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
   // frag_off(16 t, k0, K); this lane's piece is 8 lane elements further.
   const size_t arow = frag_off(m0 + wave * TM * 16, 0, A.ld) + (size_t)lane * 8;
   const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
-  uint4 ah[PD + 1][TM], al[PD + 1][TA], rbh[PD + 1][BVT], rbl[PD + 1][BVT];
+  uint4 ah[PD + 1][TM], al[PD + 1][TA], rbh[PD + 1][BVT], rbl[PD + 1][BVL];
   auto load = [&](int k0, int slot) {
     const bool in = k0 + g8 < kend;
 #pragma unroll
@@ -467,7 +536,7 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
         const int row = e / KV, k = k0 + (e % KV) * 8;
         const size_t off = (size_t)(n0 + row) * B.ld + k;
         rbh[slot][i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
-        rbl[slot][i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
+        if (ALO) rbl[slot][i] = k < kend ? *reinterpret_cast<const uint4 *>(B.lo + off) : uint4{0, 0, 0, 0};
       }
     }
   };
@@ -478,7 +547,7 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
       if (e < BV) {
         const int row = e / KV, kv = (e % KV) * 8;
         *reinterpret_cast<uint4 *>(&sBh[buf][row][kv]) = rbh[slot][i];
-        *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[slot][i];
+        if (ALO) *reinterpret_cast<uint4 *>(&sBl[buf][row][kv]) = rbl[slot][i];
       }
     }
   };
@@ -492,21 +561,23 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
     int buf = 0;
     for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
       if (k0 + PD * kBfBK < kend) load(k0 + PD * kBfBK, PD);
-      bf8v bh[TN], bl[TN];
+      bf8v bh[TN], bl[ALO ? TN : 1];
 #pragma unroll
       for (int tn = 0; tn < TN; ++tn) {
         bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][tn * 16 + r16][g8]);
-        bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][tn * 16 + r16][g8]);
+        if (ALO) bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][tn * 16 + r16][g8]);
       }
       // term-major: TM TN independent products between two on one accumulator
 #pragma unroll
       for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), bh[tn], acc[tm][tn]);
+      if (ALO) {
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm)
+        for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), bl[tn], acc[tm][tn]);
+          for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), bl[ALO ? tn : 0], acc[tm][tn]);
+      }
       if (ALO) {
 #pragma unroll
         for (int tm = 0; tm < TM; ++tm)
@@ -525,14 +596,13 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
 #pragma unroll
         for (int tm = 0; tm < TA; ++tm) al[p][tm] = al[p + 1][tm];
 #pragma unroll
-        for (int i = 0; i < BVT; ++i) {
-          rbh[p][i] = rbh[p + 1][i];
-          rbl[p][i] = rbl[p + 1][i];
-        }
+        for (int i = 0; i < BVT; ++i) rbh[p][i] = rbh[p + 1][i];
+#pragma unroll
+        for (int i = 0; i < BVL; ++i) rbl[p][i] = rbl[p + 1][i];
       }
     }
   }
-  bf_epilogue<BM, BN, WM, 1, MODE>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+  bf_epilogue<BM, BN, WM, 1, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
 }
 
 // Tile configurations of the split-K product (which = 0) and the point-row
@@ -551,7 +621,7 @@ bool gemm_bf_cfg_ok(int which, int cfg, int M, int N) {
   return M % c.bm == 0 && N % c.bn == 0;
 }
 
-template <int MODE, int TERMS>
+template <int MODE, int TERMS, int DL>
 static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, BfPair A, BfPair B,
                             int K, int kchunk, float *P, int ldp, size_t pstride,
                             const EpiArgs<float> &ea) {
@@ -559,10 +629,10 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
   const int mtiles = M / c.bm, ntiles = N / c.bn;
   const dim3 grid(mtiles * ntiles * nchunk);
 #define BF_ST(BMv, BNv, WMv, WNv, NB)                                                              \
-  hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE, NB>), grid, dim3(64 * WMv * WNv), 0, \
+  hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE, NB, DL>), grid, dim3(64 * WMv * WNv), 0, \
                      s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
 #define BF_DI(TMv, TNv, WMv)                                                                       \
-  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, TERMS, MODE>), grid, dim3(64 * WMv), 0, s, A, B, \
+  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
                      K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
   if constexpr (MODE == 0) {
     switch (cfg) {
@@ -599,24 +669,28 @@ hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int 
   kchunk = (kchunk + 31) / 32 * 32;
   const EpiArgs<float> ea{};
   const size_t pstride = (size_t)M * ldp;
-  return terms == 3 ? launch_bf<0, 3>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea)
-                    : launch_bf<0, 2>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea);
+  if (terms == 3) return launch_bf<0, 3, BF_PLAIN>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea);
+  if (terms == 1) return launch_bf<0, 1, BF_PLAIN>(cfg, M, N, nchunk, s, A, B, K, kchunk, P, ldp, pstride, ea);
+  return hipErrorInvalidValue;
 }
 
 hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
-                      const EpiArgs<float> &ea, int terms, int cfg) {
+                      const EpiArgs<float> &ea, int terms, int cfg, int delta) {
   if (!gemm_bf_cfg_ok(1, cfg, M, N)) cfg = 0;
   if (!gemm_bf_cfg_ok(1, cfg, M, N) || K % kBfBK || A.ld % 8 || B.ld % 8) return hipErrorInvalidValue;
-#define BF_EPI(E)                                                                               \
-  return terms == 3 ? launch_bf<E, 3>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)           \
-                    : launch_bf<E, 2>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)
-  switch (epi) {
-    case EPI_ADMM: BF_EPI(EPI_ADMM);
-    case EPI_ADMM_STATS: BF_EPI(EPI_ADMM_STATS);
-    case EPI_OBJ: BF_EPI(EPI_OBJ);
-    default: return hipErrorInvalidValue;
+  // the combinations the iteration uses: pairs (three terms) for BF16X3, the
+  // objective and the refresh; single operands for the hot iterations
+#define BF_EPI(E, T, D) return launch_bf<E, T, D>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)
+  if (terms == 3 && delta == BF_PLAIN) {
+    if (epi == EPI_ADMM) BF_EPI(EPI_ADMM, 3, BF_PLAIN);
+    if (epi == EPI_ADMM_STATS) BF_EPI(EPI_ADMM_STATS, 3, BF_PLAIN);
+    if (epi == EPI_OBJ) BF_EPI(EPI_OBJ, 3, BF_PLAIN);
   }
+  if (terms == 3 && delta == BF_REFRESH && epi == EPI_ADMM_STATS) BF_EPI(EPI_ADMM_STATS, 3, BF_REFRESH);
+  if (terms == 1 && delta == BF_DELTA && epi == EPI_ADMM) BF_EPI(EPI_ADMM, 1, BF_DELTA);
+  if (terms == 1 && delta == BF_DELTA_PAIR && epi == EPI_ADMM) BF_EPI(EPI_ADMM, 1, BF_DELTA_PAIR);
 #undef BF_EPI
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -684,10 +758,11 @@ hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int
   return hipGetLastError();
 }
 
-// v = sum of the S^-1 r partials; v_top as plan-major pairs (kp x ntp).
+// v = sum of the S^-1 r partials; v_top as plan-major pairs (kp x ntp), and
+// with vref (a refresh of LADMM_BF16) the value the pairs carry.
 __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,
                              double *__restrict__ v, uint16_t *__restrict__ vh,
-                             uint16_t *__restrict__ vl) {
+                             uint16_t *__restrict__ vl, double *__restrict__ vref) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const int m = blockIdx.x * 4 + threadIdx.y;
   if (m >= a.L.mAp || j >= a.kp) return;
@@ -701,13 +776,36 @@ __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t 
     split_pair(acc, h, l);
     vh[(size_t)j * a.L.ntp + m] = h;
     vl[(size_t)j * a.L.ntp + m] = l;
+    if (vref != nullptr) vref[idx] = (double)pair_val(h, l);
   }
 }
 
 hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                      double *v, uint16_t *vh, uint16_t *vl) {
+                      double *v, uint16_t *vh, uint16_t *vl, double *vref) {
   hipLaunchKernelGGL(k_vreduce_bf, dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s, a,
-                     P2, zstride, nchunk, v, vh, vl);
+                     P2, zstride, nchunk, v, vh, vl, vref);
+  return hipGetLastError();
+}
+
+// v = sum of the S^-1 r partials; dv = bf16(v_top - vref) plan-major (kp x ntp).
+__global__ void k_vreduce_delta_bf(SmallArgs a, const double *__restrict__ P2, size_t zstride,
+                                   int nchunk, double *__restrict__ v,
+                                   const double *__restrict__ vref, uint16_t *__restrict__ dv) {
+  const int j = blockIdx.y * 64 + threadIdx.x;
+  const int m = blockIdx.x * 4 + threadIdx.y;
+  if (m >= a.L.mAp || j >= a.kp) return;
+  const size_t idx = (size_t)m * a.kp + j;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int z = 0; z < nchunk; ++z) acc += P2[z * zstride + idx];
+  v[idx] = acc;
+  if (m < a.L.ntp) dv[(size_t)j * a.L.ntp + m] = bf_round((float)(acc - vref[idx]));
+}
+
+hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride,
+                            int nchunk, double *v, const double *vref, uint16_t *dv) {
+  hipLaunchKernelGGL(k_vreduce_delta_bf, dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0,
+                     s, a, P2, zstride, nchunk, v, vref, dv);
   return hipGetLastError();
 }
 
@@ -733,7 +831,8 @@ hipError_t shot_scaled_bf(hipStream_t s, const SmallArgs &a, const double *q2, u
 }
 
 __global__ void k_w_from_q_bf(const float *__restrict__ q, int Np, int kp, PointTable<float> pt,
-                              uint16_t *__restrict__ wh, uint16_t *__restrict__ wl) {
+                              uint16_t *__restrict__ wh, uint16_t *__restrict__ wl,
+                              const float *__restrict__ wref, uint16_t *__restrict__ dw) {
   const size_t total = (size_t)Np * kp;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -744,19 +843,42 @@ __global__ void k_w_from_q_bf(const float *__restrict__ q, int Np, int kp, Point
     split_pair((double)w, h, l);
     wh[(size_t)j * Np + p] = h;
     wl[(size_t)j * Np + p] = l;
+    if (dw != nullptr) dw[(size_t)j * Np + p] = bf_round(w - wref[e]);
   }
 }
 
 hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
-                       uint16_t *wh, uint16_t *wl) {
-  hipLaunchKernelGGL(k_w_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, wh, wl);
+                       uint16_t *wh, uint16_t *wl, const float *wref, uint16_t *dw) {
+  hipLaunchKernelGGL(k_w_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, wh, wl, wref, dw);
   return hipGetLastError();
 }
 
-// W' rows of warm-started plans as pairs, from their loaded q columns.
+// z1 = clip(q, 0, u) as plan-major pairs: the certificate's product operand.
+__global__ void k_z_from_q_bf(const float *__restrict__ q, int Np, int kp, PointTable<float> pt,
+                              uint16_t *__restrict__ zh, uint16_t *__restrict__ zl) {
+  const size_t total = (size_t)Np * kp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / kp), j = (int)(e % kp);
+    uint16_t h, l;
+    split_pair((double)clip0u_f(q[e], upper_bf(pt, pt.grp[p], p, j)), h, l);
+    zh[(size_t)j * Np + p] = h;
+    zl[(size_t)j * Np + p] = l;
+  }
+}
+
+hipError_t z_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
+                       uint16_t *zh, uint16_t *zl) {
+  hipLaunchKernelGGL(k_z_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, zh, zl);
+  return hipGetLastError();
+}
+
+// W' rows of warm-started plans as pairs, from their loaded q columns (and
+// dW = bf16(W' - W_ref) with wref, dw: LADMM_BF16).
 __global__ void k_warm_w_bf(WarmCols w, const float *__restrict__ q, int Np, int kp,
                             PointTable<float> pt, uint16_t *__restrict__ wh,
-                            uint16_t *__restrict__ wl) {
+                            uint16_t *__restrict__ wl, const float *__restrict__ wref,
+                            uint16_t *__restrict__ dw) {
   const int i = blockIdx.y;
   if (i >= w.n) return;
   const int j = w.col[i];
@@ -768,28 +890,32 @@ __global__ void k_warm_w_bf(WarmCols w, const float *__restrict__ q, int Np, int
   split_pair((double)wv, h, l);
   wh[(size_t)j * Np + p] = h;
   wl[(size_t)j * Np + p] = l;
+  if (dw != nullptr) dw[(size_t)j * Np + p] = bf_round(wv - wref[(size_t)p * kp + j]);
 }
 
 hipError_t warm_w_bf(hipStream_t s, const WarmCols &w, const float *q, uint16_t *wh, uint16_t *wl,
-                     int Np, int kp, const PointTable<float> &pt) {
+                     int Np, int kp, const PointTable<float> &pt, const float *wref, uint16_t *dw) {
   if (w.n <= 0) return hipSuccess;
   if (w.n > kWarmCols) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_warm_w_bf, dim3((unsigned)((Np + 255) / 256), (unsigned)w.n), dim3(256), 0, s,
-                     w, q, Np, kp, pt, wh, wl);
+                     w, q, Np, kp, pt, wh, wl, wref, dw);
   return hipGetLastError();
 }
 
-// Zero the rows j (hi and lo) of plan-major pairs (2 kp rows of len) whose
-// flag[j] is nonzero: a fresh plan in a reused column.
-__global__ void k_zero_plan_rows(uint16_t *__restrict__ a, int kp, int len, const int32_t *__restrict__ flag) {
-  const size_t total = (size_t)2 * kp * len;
+// Zero the rows j of plan-major BF16 arrays (halves x kp rows of len: hi then
+// lo rows of pairs, or one single array) whose flag[j] is nonzero: a fresh
+// plan in a reused column.
+__global__ void k_zero_plan_rows(uint16_t *__restrict__ a, int kp, int len, int halves,
+                                 const int32_t *__restrict__ flag) {
+  const size_t total = (size_t)halves * kp * len;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x)
     if (flag[(e / len) % kp]) a[e] = 0;
 }
 
-hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const int32_t *flag) {
-  hipLaunchKernelGGL(k_zero_plan_rows, dim3(2048), dim3(256), 0, s, a, kp, len, flag);
+hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const int32_t *flag,
+                             int halves) {
+  hipLaunchKernelGGL(k_zero_plan_rows, dim3(2048), dim3(256), 0, s, a, kp, len, halves, flag);
   return hipGetLastError();
 }
 

@@ -440,6 +440,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_nn(const T *__restrict__ 
           } else {
             const double h = fmax(0.0, (double)sg - (double)s);
             st[tm][tn][0] = fma((double)u, h, st[tm][tn][0]);
+            if (sg > T(0)) st[tm][tn][2] = fma((double)u, (double)s, st[tm][tn][2]);
           }
         } else {
           T *qp = ea.q + (size_t)m * ea.ldq + n;

@@ -49,7 +49,7 @@ hipError_t gemm_tn(hipStream_t s, const T *A, int lda, const T *B, int ldb, T *P
 // Epilogues of C = A B (A: M x K row-major, B: K x N row-major).
 enum { EPI_STORE = 0, EPI_ADMM = 1, EPI_ADMM_STATS = 2, EPI_OBJ = 3 };
 constexpr int kAdmmStats = 6;   // (x-z)^2, x^2, z^2, (z-zprev)^2, y^2, c'z
-constexpr int kObjStats = 2;    // hinge sum, OAR dose ratio max
+constexpr int kObjStats = 3;    // hinge sum, OAR dose ratio max, sum of u d / D over targets
 template <typename T>
 struct EpiArgs {
   T *C; int ldc;                   // EPI_STORE output
@@ -61,6 +61,11 @@ struct EpiArgs {
   PointTable<T> pt;
   uint16_t *wt_hi, *wt_lo; int ldwt;   // BF16-pair products: W' = z1' - y1' as plans x points
   double alpha;                    // over-relaxation of the z- and y-steps (1: none)
+  // BF16 refinement (LADMM_BF16): the exact products at the last refresh,
+  // X_ref = D^ v_ref and W_ref (points x plans, ld = ldq), and the change
+  // dW = bf16(W' - W_ref) written plan-major (ld = ldwt) for the next GEMM1.
+  float *xref, *wref;
+  uint16_t *dw;
 };
 template <typename T>
 hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int ldb,
@@ -98,10 +103,14 @@ struct SmallArgs {
   int kp;
   double alpha;         // over-relaxation of the z- and y-steps (1: none)
 };
-// r = A_s W + g / rho - (2 clip(q2) - q2), from the GEMM1 partials.
+// r = A_s W + g / rho - (2 clip(q2) - q2), from the GEMM1 partials.  The
+// dose-point part G = sum of the partials; with gref (the BF16 refinement's hot
+// iterations) G = gref + partials (the product of the change since the last
+// refresh), and with gout (its refresh) G is also stored there.
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
-               const double *qs, const double *q2, double *r);
+               const double *qs, const double *q2, double *r, const double *gref = nullptr,
+               double *gout = nullptr);
 // v = sum of the Sinv r partials (mAp x kp) and vT = (T) v_top (ntp x kp).
 template <typename T>
 hipError_t vreduce(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
@@ -121,10 +130,23 @@ struct FinalArgs {
   const double *obj_stats; int obj_blocks;
   const double *q2; const double *E; const double *invrho; const double *wbot;
   SmallLayout L; double cs; int kp;
+  // certificate (NULL: none): per shot column and plan, the smallest sector
+  // value that column's shot row allows for the dual point x = clip(z1)
+  const double *need;   // ntp x kp
   double *out;   // kp x kFinal
 };
-constexpr int kFinal = 8;   // F, c'z, gap, r_pri, r_dual, oar_ratio, bot_sum, hinge
+// F, c'z, gap, r_pri, r_dual, oar_ratio, bot_sum, hinge, lower bound L, certified gap
+constexpr int kFinal = 10;
 hipError_t finalize(hipStream_t s, const FinalArgs &a);
+// Certified bounds of a check (App. A duality): z1 = clip(q, 0, u) of the dose
+// points as the operand of a split-K product with the dose block, then
+// need[t][j] = max(0, (D~' z1)_t) D_T / phi_cal from its partials (E_t scales
+// them back from the scaled block).  z_from_q writes z1 point-major (Np x kp, T).
+template <typename T>
+hipError_t z_from_q(hipStream_t s, const T *q, T *z, int Np, int kp, const PointTable<T> &pt);
+template <typename T>
+hipError_t cert_need(hipStream_t s, const SmallArgs &a, const T *P, size_t zstride, int nchunk,
+                     double *need);
 // t[j][t] = E_t rho_j max(q2_t, 0) (k x n_t, double)
 hipError_t extract_t(hipStream_t s, const SmallArgs &a, const double *q2, double *t, int k);
 
@@ -172,30 +194,53 @@ hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const doubl
 // An FP32/FP64 operand x is carried as the pair hi = bf16(x), lo = bf16(x - hi)
 // (16 significant bits); both operands are stored row-major with the
 // reduction index contiguous (A: M x K rows, B: N x K rows).  A product sums
-// A_hi B_hi + A_hi B_lo (+ A_lo B_hi with terms = 3) on the BF16 MFMA with FP32
+// A_hi B_hi + A_hi B_lo + A_lo B_hi (terms = 3) or A_hi B_hi alone (terms = 1,
+// a single BF16 operand on each side) on the BF16 MFMA with FP32
 // accumulation, in the same order for every tile configuration.
 struct BfPair { const uint16_t *hi, *lo; int ld; };
 bool gemm_bf_cfg_ok(int which, int cfg, int M, int N);   // which: 0 split-K, 1 point-row
 // P[z][m][n] = sum over rows k of chunk z of A[m][k] B[n][k]  (split-K partials, FP32)
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg);
-// C = A B' with the ADMM / statistics / objective epilogues (W' written as pairs)
+// Epilogue variants of the point-row product for the BF16 refinement mode
+// (LADMM_BF16).  The hot iterations multiply single BF16 operands by the
+// change since the last refresh; a refresh iteration runs the three-term
+// products and records the references.
+enum {
+  BF_PLAIN = 0,     // pairs in and out (LADMM_BF16X3; also the objective product)
+  BF_DELTA = 1,     // product = X_ref + D_hi dv; writes dW = bf16(W' - W_ref)
+  BF_DELTA_PAIR = 2,// product = X_ref + D_hi dv; writes W' as pairs (a refresh follows)
+  BF_REFRESH = 3    // three-term product; X_ref := product, W_ref := W (pairs' value);
+                    // writes W' as pairs and dW
+};
+// C = A B' with the ADMM / statistics / objective epilogues
 hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
-                      const EpiArgs<float> &ea, int terms, int cfg);
+                      const EpiArgs<float> &ea, int terms, int cfg, int delta = BF_PLAIN);
 // D^ = Dt diag(E) as pairs in fragment order (16-row tiles x 32-wide k steps,
 // 1 KiB per fragment), point-major (Np x ntp) and shot-major (ntp x Np).
 hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int Np, int ntp,
                            uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl);
 // v_top and the scaled shot times as plan-major pairs (kp x ntp) for the products.
+// With vref != NULL (a refresh): also vref := hi + lo (the value the pairs carry).
 hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                      double *v, uint16_t *vh, uint16_t *vl);
+                      double *v, uint16_t *vh, uint16_t *vl, double *vref = nullptr);
+// v and dv = bf16(v_top - vref) plan-major (kp x ntp): the hot iterations of LADMM_BF16.
+hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride,
+                            int nchunk, double *v, const double *vref, uint16_t *dv);
 hipError_t shot_scaled_bf(hipStream_t s, const SmallArgs &a, const double *q2, uint16_t *th,
                           uint16_t *tl);
-// Zero rows j (hi and lo) of plan-major pairs (2 kp rows of len) with flag[j] != 0.
-hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const int32_t *flag);
-// W' pairs (kp x Np) from q after a state import.
+// z1 = clip(q, 0, u) as plan-major pairs (kp x Np), the certificate's operand.
+hipError_t z_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
+                       uint16_t *zh, uint16_t *zl);
+// Zero rows j of plan-major BF16 arrays (halves x kp rows of len: 2 for pairs,
+// hi rows then lo rows; 1 for a single array) with flag[j] != 0.
+hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const int32_t *flag,
+                             int halves = 2);
+// W' pairs (kp x Np) from q after a state import; with wref and dw (LADMM_BF16)
+// also dw = bf16(W' - W_ref).
 hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
-                       uint16_t *wh, uint16_t *wl);
+                       uint16_t *wh, uint16_t *wl, const float *wref = nullptr,
+                       uint16_t *dw = nullptr);
 
 // Zero the columns j of a (rows x ld, row-major) whose flag[j] is nonzero:
 // the start of a fresh plan in a reused column.

@@ -232,6 +232,13 @@ int upload(Lane &L) {
     } else {   // W' is held as plan-major BF16 pairs
       HIPC(zero_columns<float>(s, (float *)b->q, c->Np, kp, L.d_reset));
       HIPC(zero_plan_rows_bf(s, (uint16_t *)b->W, kp, c->Np, L.d_reset));
+      if (c->precision == LADMM_BF16) {   // a fresh plan's references are zero too
+        HIPC(zero_columns<float>(s, b->xref, c->Np, kp, L.d_reset));
+        HIPC(zero_columns<float>(s, b->wref, c->Np, kp, L.d_reset));
+        HIPC(zero_columns<double>(s, b->gref, c->ntp, kp, L.d_reset));
+        HIPC(zero_columns<double>(s, b->vref, c->ntp, kp, L.d_reset));
+        HIPC(zero_plan_rows_bf(s, b->dW, kp, c->Np, L.d_reset, 1));
+      }
     }
     HIPC(zero_columns<double>(s, b->qs, c->n_sec, kp, L.d_reset));
     HIPC(zero_columns<double>(s, b->q2, c->mAp, kp, L.d_reset));
@@ -253,7 +260,7 @@ int upload(Lane &L) {
         } else {
           uint16_t *wh = (uint16_t *)b->W;
           HIPC(warm_w_bf(s, wc, (const float *)b->q, wh, wh + (size_t)kp * c->Np, c->Np, kp,
-                         point_table<float>(b)));
+                         point_table<float>(b), b->wref, b->dW));
         }
       }
       wc.n = 0;
@@ -496,6 +503,8 @@ int retire(ladmm_server *sv, Lane &L, std::vector<Request *> *touched) {
     if (o.r_dual) o.r_dual[p] = f[4];
     if (o.iters) o.iters[p] = b->iters[s];
     if (o.plan_status) o.plan_status[p] = b->status[s];
+    if (o.lower_bound) o.lower_bound[p] = f[8];
+    if (o.cert_gap) o.cert_gap[p] = f[9];
     L.owner[s] = nullptr;
     L.plan[s] = -1;
     L.dirty = true;

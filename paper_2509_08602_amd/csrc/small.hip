@@ -327,7 +327,8 @@ hipError_t tri_inverse(hipStream_t s, const double *L, double *X, int n, int ld)
 template <typename T>
 __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int nchunk,
                       const double *__restrict__ qs, const double *__restrict__ q2,
-                      double *__restrict__ r) {
+                      double *__restrict__ r, const double *__restrict__ gref,
+                      double *__restrict__ gout) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const int m = blockIdx.x * 4 + threadIdx.y;
   const SmallLayout &L = a.L;
@@ -339,6 +340,8 @@ __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int
     // the partials are independent loads: keep several in flight
 #pragma unroll 8
     for (int z = 0; z < nchunk; ++z) g += (double)P1[z * zstride + (size_t)m * kp + j];
+    if (gout != nullptr) gout[(size_t)m * kp + j] = g;
+    if (gref != nullptr) g += gref[(size_t)m * kp + j];
     const int sec = m / L.C;
     const double qsv = qs[(size_t)sec * kp + j];
     const double wsec = 2.0 * fmax(qsv, 0.0) - qsv;       // z1 - y1 of the sector variable
@@ -361,13 +364,13 @@ __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int
 
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
-               const double *qs, const double *q2, double *r) {
+               const double *qs, const double *q2, double *r, const double *gref, double *gout) {
   hipLaunchKernelGGL((k_rhs<T>), dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s, a, P1,
-                     zstride, nchunk, qs, q2, r);
+                     zstride, nchunk, qs, q2, r, gref, gout);
   return hipGetLastError();
 }
-template hipError_t rhs<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, const double *, const double *, double *);
-template hipError_t rhs<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, const double *, const double *, double *);
+template hipError_t rhs<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, const double *, const double *, double *, const double *, double *);
+template hipError_t rhs<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, const double *, const double *, double *, const double *, double *);
 
 template <typename T>
 __global__ void k_vreduce(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,
@@ -492,6 +495,58 @@ hipError_t shot_scaled(hipStream_t s, const SmallArgs &a, const double *q2, T *t
 template hipError_t shot_scaled<float>(hipStream_t, const SmallArgs &, const double *, float *);
 template hipError_t shot_scaled<double>(hipStream_t, const SmallArgs &, const double *, double *);
 
+// need[t][j] = max(0, (D~' z1)_t) D_T / phi_cal: the smallest value of sector
+// (i, s) that shot row t = (i, s, c) allows (App. A: phi' x - C_S' x_sec <= 0),
+// from the split-K partials of (D^' z1)_t = E_t (D~' z1)_t.
+template <typename T>
+__global__ void k_cert_need(SmallArgs a, const T *__restrict__ P, size_t zstride, int nchunk,
+                            double *__restrict__ need) {
+  const int j = blockIdx.y * 64 + threadIdx.x;
+  const int m = blockIdx.x * 4 + threadIdx.y;
+  if (m >= a.L.ntp || j >= a.kp) return;
+  double v = 0.0;
+  if (m < a.L.n_t) {
+    double g = 0.0;
+#pragma unroll 8
+    for (int z = 0; z < nchunk; ++z) g += (double)P[z * zstride + (size_t)m * a.kp + j];
+    v = fmax(0.0, g / a.E[m]) / a.cs;
+  }
+  need[(size_t)m * a.kp + j] = v;
+}
+
+template <typename T>
+hipError_t cert_need(hipStream_t s, const SmallArgs &a, const T *P, size_t zstride, int nchunk,
+                     double *need) {
+  hipLaunchKernelGGL((k_cert_need<T>), dim3((a.L.ntp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s,
+                     a, P, zstride, nchunk, need);
+  return hipGetLastError();
+}
+template hipError_t cert_need<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, double *);
+template hipError_t cert_need<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, double *);
+
+template <typename T>
+__global__ void k_z_from_q(const T *__restrict__ q, T *__restrict__ z, int Np, int kp, PointTable<T> pt) {
+  const size_t total = (size_t)Np * kp;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / kp), j = (int)(e % kp);
+    T u = pt.utab[(size_t)pt.grp[p] * pt.ldu + j];
+    if (pt.mask != nullptr && pt.is_ld[pt.grp[p]]) {
+      const uint64_t w = pt.mask[(size_t)j * pt.mask_words + (p >> 6)];
+      if (!((w >> (p & 63)) & 1ull)) u = T(0);
+    }
+    z[e] = fmin(fmax(q[e], T(0)), u);
+  }
+}
+
+template <typename T>
+hipError_t z_from_q(hipStream_t s, const T *q, T *z, int Np, int kp, const PointTable<T> &pt) {
+  hipLaunchKernelGGL((k_z_from_q<T>), dim3(2048), dim3(256), 0, s, q, z, Np, kp, pt);
+  return hipGetLastError();
+}
+template hipError_t z_from_q<float>(hipStream_t, const float *, float *, int, int, const PointTable<float> &);
+template hipError_t z_from_q<double>(hipStream_t, const double *, double *, int, int, const PointTable<double> &);
+
 __device__ double block_sum(double v, double *sh) {
   const int tid = threadIdx.x;
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -535,8 +590,12 @@ __global__ void k_finalize(FinalArgs a) {
     hinge += a.obj_stats[((size_t)b * kObjStats + 0) * kp + j];
     oar = fmax(oar, a.obj_stats[((size_t)b * kObjStats + 1) * kp + j]);
   }
+  double tdose = 0.0;   // sum over targets of u d / D (the OAR repair of the upper bound)
+  for (int b = tid; b < a.obj_blocks; b += blockDim.x)
+    tdose += a.obj_stats[((size_t)b * kObjStats + 2) * kp + j];
   hinge = block_sum(hinge, sh);
   oar = block_max(oar, sh);
+  tdose = block_sum(tdose, sh);
   // beam-on time: tau_i = (phi_cal / D_T) max_s sum_c t_isc, t = E rho max(q2, 0)
   const double ir = a.invrho[j];
   const double rho = ir > 0.0 ? 1.0 / ir : 0.0;
@@ -554,6 +613,30 @@ __global__ void k_finalize(FinalArgs a) {
     bot += a.cs * best;
   }
   bot = block_sum(bot, sh);
+  // Certificate: the dual point x = (clip(z1), smallest sector values) needs
+  // per isocentre i the sum over sectors of the largest collimator value of
+  // need; theta = min(1, min_i w_BOT / that sum) keeps every BOT row feasible,
+  // and L = -c'(theta x) = -theta c'z1 (c is zero on the sector block).
+  double ratio = INFINITY;
+  if (a.need != nullptr) {
+    const double wb = a.wbot[j];
+    for (int i = tid; i < a.L.n_iso; i += blockDim.x) {
+      double sum = 0.0;
+      for (int s = 0; s < a.L.S; ++s) {
+        double best = 0.0;
+        for (int c = 0; c < a.L.C; ++c)
+          best = fmax(best, a.need[(size_t)((i * a.L.S + s) * a.L.C + c) * kp + j]);
+        sum += best;
+      }
+      if (sum > 0.0) ratio = fmin(ratio, wb / sum);
+    }
+    for (int o = 32; o > 0; o >>= 1) ratio = fmin(ratio, __shfl_xor(ratio, o));
+    if ((tid & 63) == 0) sh[tid >> 6] = ratio;
+    __syncthreads();
+    if (tid == 0)
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) ratio = fmin(ratio, sh[w]);
+    __syncthreads();
+  }
   if (tid == 0) {
     const double F = hinge + a.wbot[j] * bot;
     const double cz = s6[5];
@@ -566,6 +649,18 @@ __global__ void k_finalize(FinalArgs a) {
     o[5] = oar;
     o[6] = bot;
     o[7] = hinge;
+    if (a.need != nullptr) {
+      const double theta = fmin(1.0, ratio);
+      const double L = -theta * cz;
+      // OAR-feasible shot times t / r scale every dose by 1 / r: only the
+      // target hinges grow, each by at most (1 - 1/r) u d / D
+      const double U = oar > 1.0 ? F + (1.0 - 1.0 / oar) * tdose : F;
+      o[8] = L;
+      o[9] = (U - L) / fmax(U, 1e-300);
+    } else {
+      o[8] = NAN;
+      o[9] = NAN;
+    }
   }
 }
 

@@ -34,12 +34,15 @@ int fail(int code, const std::string &msg);
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Precision modes whose dose block is held as BF16 pairs (products on the BF16 MFMA).
+inline bool bf16_block(int precision) { return precision == LADMM_BF16X3 || precision == LADMM_BF16; }
+
 // Stopping rule of one plan column: converged at a check where rel_gap,
 // r_pri and r_dual are within their tolerances (tol_gap <= 0: never), and
 // stopped at max_iter iterations of its own.
 struct StopRule {
   int32_t max_iter;
-  double tol_gap, tol_pri, tol_dual;
+  double tol_gap, tol_pri, tol_dual, tol_cert;
   // step-size balancing (adapt = 0: the fixed rule); rho kept in [rho_lo, rho_hi]
   int32_t adapt;
   double mu, tau, rho_lo, rho_hi;
@@ -47,8 +50,20 @@ struct StopRule {
 
 // The stopping and step-size rule of a plan that starts with step size rho.
 inline StopRule make_rule(const ladmm_opts &o, int32_t max_iter, double rho) {
-  return StopRule{max_iter, o.tol_gap, o.tol_pri, o.tol_dual, o.adapt_rho, o.adapt_mu, o.adapt_tau,
-                  rho * 1e-3, rho * 1e3};
+  return StopRule{max_iter, o.tol_gap, o.tol_pri, o.tol_dual, o.tol_cert, o.adapt_rho, o.adapt_mu,
+                  o.adapt_tau, rho * 1e-3, rho * 1e3};
+}
+
+// Whether a plan's statistics at a check (kFinal values: F, c'z, gap, r_pri,
+// r_dual, oar, bot, hinge, L, cert gap) meet its stopping rule: every
+// tolerance in use holds, and at least one of tol_gap, tol_cert is in use.
+inline bool rule_met(const StopRule &r, const double *f) {
+  if (!(r.tol_gap > 0) && !(r.tol_cert > 0)) return false;
+  if (r.tol_gap > 0 && !(f[2] <= r.tol_gap)) return false;
+  if (r.tol_cert > 0 && !(f[9] <= r.tol_cert)) return false;
+  if (r.tol_pri > 0 && !(f[3] <= r.tol_pri)) return false;
+  if (r.tol_dual > 0 && !(f[4] <= r.tol_dual)) return false;
+  return true;
 }
 
 }  // namespace ladmm
@@ -70,7 +85,7 @@ struct ladmm_case {
   int row_normalize = 1;
   ladmm::SmallLayout L{};
   void *D = nullptr;         // Np x ntp, scaled point block of A' (precision T)
-  // LADMM_BF16X3: the same block as BF16 pairs, point-major and shot-major
+  // LADMM_BF16X3 and LADMM_BF16: the same block as BF16 pairs, point-major and shot-major
   const uint16_t *Dh = nullptr, *Dl = nullptr, *DTh = nullptr, *DTl = nullptr;
   void *sig = nullptr;       // Np (T)
   int32_t *grp = nullptr;    // Np
@@ -112,6 +127,15 @@ struct ladmm_batch {
   void *P1 = nullptr;
   double *r = nullptr, *P2 = nullptr, *v = nullptr;
   void *vT = nullptr, *that = nullptr;
+  // LADMM_BF16 (refinement): references of the last refresh and the change of
+  // W since it (plan-major, kp x Np)
+  float *xref = nullptr, *wref = nullptr;   // Np x kp
+  double *gref = nullptr, *vref = nullptr;  // ntp x kp
+  uint16_t *dW = nullptr;
+  // certificate of a check: z1 of the dose points (point-major T, or plan-major
+  // pairs for the BF16 blocks) and the smallest sector values of the dual point
+  void *zc = nullptr;
+  double *need = nullptr;     // ntp x kp
   double *admm_stats = nullptr, *post_stats = nullptr, *obj_stats = nullptr, *fin = nullptr;
   int admm_blocks = 0, post_blocks = 0, obj_blocks = 0;
   std::vector<void *> allocs;

@@ -27,8 +27,10 @@ hipError_t warm_load(hipStream_t s, const WarmCols &w, const T *wq, const double
 template <typename T>
 hipError_t warm_w(hipStream_t s, const WarmCols &w, const T *q, T *W, int Np, int kp,
                   const PointTable<T> &pt);
-// The same for W' held as plan-major BF16 pairs (rows j: hi, rows kp + j: lo).
+// The same for W' held as plan-major BF16 pairs (rows j: hi, rows kp + j: lo);
+// with wref and dw (LADMM_BF16) also dW = bf16(W' - W_ref) of those columns.
 hipError_t warm_w_bf(hipStream_t s, const WarmCols &w, const float *q, uint16_t *wh, uint16_t *wl,
-                     int Np, int kp, const PointTable<float> &pt);
+                     int Np, int kp, const PointTable<float> &pt, const float *wref = nullptr,
+                     uint16_t *dw = nullptr);
 
 }  // namespace ladmm

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libladmm.so")
 
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE, E_CANCELLED = -1, -2, -3, -4, -5, -6
-F64, F32, BF16X3 = 0, 1, 2
+F64, F32, BF16X3, BF16 = 0, 1, 2, 3
 PT_TS, PT_TI, PT_RING, PT_LD, PT_OAR = 0, 1, 2, 3, 4
 PLAN_CONVERGED, PLAN_MAX_ITER, PLAN_NUMERIC, PLAN_RUNNING = 0, 1, 2, 3
-PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "bf16": BF16}
 
 
 class LadmmError(RuntimeError):
@@ -54,7 +54,8 @@ class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("tol_gap", C.c_double),
                 ("tol_pri", C.c_double), ("tol_dual", C.c_double), ("rho0", C.c_double),
                 ("w0_bot", C.c_double), ("autotune", C.c_int32), ("adapt_rho", C.c_int32),
-                ("adapt_mu", C.c_double), ("adapt_tau", C.c_double), ("alpha", C.c_double)]
+                ("adapt_mu", C.c_double), ("adapt_tau", C.c_double), ("alpha", C.c_double),
+                ("tol_cert", C.c_double)]
 
 
 _DP = C.POINTER(C.c_double)
@@ -70,7 +71,7 @@ class _Pass2(C.Structure):
 class _Result(C.Structure):
     _fields_ = [("t", _DP), ("bot", _DP), ("objective", _DP), ("dual_obj", _DP),
                 ("rel_gap", _DP), ("r_pri", _DP), ("r_dual", _DP), ("iters", _IP),
-                ("plan_status", _IP)]
+                ("plan_status", _IP), ("lower_bound", _DP), ("cert_gap", _DP)]
 
 
 class _ServerOpts(C.Structure):
@@ -126,6 +127,7 @@ _SIGS = {
     "ladmm_batch_export": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
+    "ladmm_batch_step_sizes": (C.c_int, [C.c_void_p, _DP]),
     "ladmm_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_metrics": (C.c_int, [C.c_void_p, C.c_int64, _DP, _IP, C.c_int32, _DP, C.c_double,
                                       _DP]),
@@ -208,12 +210,14 @@ class Options:
     adapt_mu: float = 10.0
     adapt_tau: float = 2.0
     alpha: float = 1.0         # over-relaxation (1: the paper's ADMM)
+    tol_cert: float = 0.0      # > 0: also stop only at a certified gap <= tol_cert
 
     def c(self):
         return _Opts(int(self.max_iter), int(self.check_every), float(self.tol_gap),
                      float(self.tol_pri), float(self.tol_dual), float(self.rho0),
                      float(self.w0_bot), 1 if self.autotune else 0, 1 if self.adapt_rho else 0,
-                     float(self.adapt_mu), float(self.adapt_tau), float(self.alpha))
+                     float(self.adapt_mu), float(self.adapt_tau), float(self.alpha),
+                     float(self.tol_cert))
 
 
 class Context:
@@ -354,16 +358,7 @@ class Batch:
 
     def results(self, with_t=True):
         k, c = self.k, self.case
-        out = dict(objective=np.empty(k), dual_obj=np.empty(k), rel_gap=np.empty(k),
-                   r_pri=np.empty(k), r_dual=np.empty(k), iters=np.empty(k, np.int32),
-                   plan_status=np.empty(k, np.int32))
-        if with_t:
-            out["t"] = np.empty((k, c.n_t))
-            out["bot"] = np.empty((k, c.n_iso))
-        r = _Result(_dptr(out.get("t")), _dptr(out.get("bot")), _dptr(out["objective"]),
-                    _dptr(out["dual_obj"]), _dptr(out["rel_gap"]), _dptr(out["r_pri"]),
-                    _dptr(out["r_dual"]), out["iters"].ctypes.data_as(_IP),
-                    out["plan_status"].ctypes.data_as(_IP))
+        out, r = _result_buffers(k, c.n_t, c.n_iso, with_t)
         _check(library().ladmm_batch_results(self._h, C.byref(r)))
         return out
 
@@ -385,8 +380,13 @@ class Batch:
         _check(library().ladmm_batch_timing(self._h, C.byref(ms), C.byref(pit)))
         return ms.value, pit.value
 
+    def step_sizes(self):
+        rho = np.empty(self.k)
+        _check(library().ladmm_batch_step_sizes(self._h, _dptr(rho)))
+        return rho
+
     KERNEL_CLASSES = ("gemm1", "rhs", "schur_solve", "post", "gemm2", "objective",
-                      "shot_scale", "finalize")
+                      "shot_scale", "finalize", "certificate", "gemm1_refresh", "gemm2_refresh")
 
     def tiles(self):
         a, b = C.c_int32(), C.c_int32()
@@ -446,13 +446,19 @@ class Batch:
             pass
 
 
-def _result_buffers(k, n_t, n_iso):
-    out = dict(t=np.empty((k, n_t)), bot=np.empty((k, n_iso)), objective=np.empty(k),
-               dual_obj=np.empty(k), rel_gap=np.empty(k), r_pri=np.empty(k), r_dual=np.empty(k),
-               iters=np.empty(k, np.int32), plan_status=np.empty(k, np.int32))
-    r = _Result(_dptr(out["t"]), _dptr(out["bot"]), _dptr(out["objective"]), _dptr(out["dual_obj"]),
-                _dptr(out["rel_gap"]), _dptr(out["r_pri"]), _dptr(out["r_dual"]),
-                out["iters"].ctypes.data_as(_IP), out["plan_status"].ctypes.data_as(_IP))
+def _result_buffers(k, n_t, n_iso, with_t=True):
+    """Host result arrays of k plans and the ladmm_result that points at them."""
+    out = dict(objective=np.empty(k), dual_obj=np.empty(k), rel_gap=np.empty(k),
+               r_pri=np.empty(k), r_dual=np.empty(k), iters=np.empty(k, np.int32),
+               plan_status=np.empty(k, np.int32), lower_bound=np.empty(k), cert_gap=np.empty(k))
+    if with_t:
+        out["t"] = np.empty((k, n_t))
+        out["bot"] = np.empty((k, n_iso))
+    r = _Result(_dptr(out.get("t")), _dptr(out.get("bot")), _dptr(out["objective"]),
+                _dptr(out["dual_obj"]), _dptr(out["rel_gap"]), _dptr(out["r_pri"]),
+                _dptr(out["r_dual"]), out["iters"].ctypes.data_as(_IP),
+                out["plan_status"].ctypes.data_as(_IP), _dptr(out["lower_bound"]),
+                _dptr(out["cert_gap"]))
     return out, r
 
 
@@ -562,12 +568,7 @@ def solve_batch(case: Case, weights, ld_mask=None, opts: Options | None = None):
     mask = _mask_words(ld_mask, case.n_points)
     mp = mask.ctypes.data_as(C.POINTER(C.c_uint64)) if mask is not None else None
     o = (opts or Options()).c()
-    out = dict(t=np.empty((k, case.n_t)), bot=np.empty((k, case.n_iso)), objective=np.empty(k),
-               dual_obj=np.empty(k), rel_gap=np.empty(k), r_pri=np.empty(k), r_dual=np.empty(k),
-               iters=np.empty(k, np.int32), plan_status=np.empty(k, np.int32))
-    r = _Result(_dptr(out["t"]), _dptr(out["bot"]), _dptr(out["objective"]), _dptr(out["dual_obj"]),
-                _dptr(out["rel_gap"]), _dptr(out["r_pri"]), _dptr(out["r_dual"]),
-                out["iters"].ctypes.data_as(_IP), out["plan_status"].ctypes.data_as(_IP))
+    out, r = _result_buffers(k, case.n_t, case.n_iso)
     _check(library().ladmm_solve_batch(case._h, k, w, mp, C.byref(o), C.byref(r)))
     return out
 

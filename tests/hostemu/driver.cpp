@@ -92,10 +92,10 @@ int main(int argc, char **argv) {
   save(dir + "/y1.f64", y1.data(), y1.size());
   save(dir + "/z2.f64", z2.data(), z2.size());
   save(dir + "/y2.f64", y2.data(), y2.size());
-  std::vector<double> res((size_t)k * 5), t((size_t)k * n_t), bot((size_t)k * n_iso);
+  std::vector<double> res((size_t)k * 7), t((size_t)k * n_t), bot((size_t)k * n_iso);
   std::vector<int32_t> it(k), st(k);
   ladmm_result r{t.data(), bot.data(), &res[0], &res[k], &res[2 * k], &res[3 * k], &res[4 * k],
-                 it.data(), st.data()};
+                 it.data(), st.data(), &res[5 * k], &res[6 * k]};
   CHECK(ladmm_batch_results(b, &r));
   save(dir + "/res.f64", res.data(), res.size());
   save(dir + "/t.f64", t.data(), t.size());

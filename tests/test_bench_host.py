@@ -60,3 +60,16 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert out.returncode == 2
     assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_algorithmic_bytes_of_the_hot_products():
+    """The byte model of the roofline: the dose block once at its storage
+    width, the plan-side operand and the result traffic."""
+    N, n_t, k, kp = 1000, 192, 9, 32
+    # BF16 refinement: 2-byte dose block; GEMM2 reads q, X_ref, W_ref and writes q and dW
+    assert bench.product_bytes("gemm2", "bf16", N, n_t, k, kp) == 2 * N * n_t + 2 * n_t * kp + 18 * N * kp
+    assert bench.product_bytes("gemm1", "bf16", N, n_t, k, kp) == 2 * N * n_t + 2 * N * kp + 4 * n_t * kp
+    # FP32: 4-byte block, q read and written and W written
+    assert bench.product_bytes("gemm2", "f32", N, n_t, k, kp) == 4 * N * n_t + 4 * n_t * kp + 12 * N * kp
+    info = bench.host_cpu()
+    assert info["nproc"] >= 1

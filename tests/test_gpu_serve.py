@@ -92,7 +92,8 @@ def test_served_plans_equal_plans_solved_alone(ctx, c0, mini):
         assert abs(F[j] - fs) <= 1e-3 * abs(fs) + 1e-9, (j, F[j], fs)
 
 
-@pytest.mark.parametrize("precision,eager", [("f32", False), ("bf16x3", False), ("f32", True)])
+@pytest.mark.parametrize("precision,eager", [("f32", False), ("bf16x3", False), ("bf16", False),
+                                             ("f32", True)])
 def test_slot_reuse_and_masks_match_alone(ctx, mini, precision, eager):
     """More plans than slots (plans start in freed slots), with LD masks.  The
     lanes replay captured graphs (or, eager, launch one by one); the requests
@@ -179,7 +180,7 @@ def test_hbm_budget_evicts_idle_lanes(ctx, mini, c0):
     same(res[2], ladmm.solve_batch(ca, w[3:], opts=o))
 
 
-@pytest.mark.parametrize("precision", ["f64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["f64", "bf16x3", "bf16"])
 def test_warm_start_from_nearest_solved_plan(ctx, c0, precision):
     """A server with a warm store starts each admitted plan from the stored
     solved plan of the nearest weighting.  The 9 slider plans solved a second

@@ -65,7 +65,7 @@ def driver():
     return exe
 
 
-PRECISION = {"f64": 0, "f32": 1, "bf16x3": 2}
+PRECISION = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
 
 
 def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, seed=0,
@@ -116,7 +116,12 @@ def small_case(seed=0, oar=False):
 ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
               ("f32", 2e-3, (-1, -1), 12, 5),
               ("bf16x3", 2e-4, (-1, -1), 0, 5),
-              ("bf16x3", 2e-4, (4, 4), 0, 70)]
+              ("bf16x3", 2e-4, (4, 4), 0, 70),
+              # single BF16 products of the change since the last refresh: from
+              # zero iterates the first changes are the full values, so the
+              # iterates carry BF16 rounding (2^-9 relative per operand) until
+              # the refresh that ends the chunk
+              ("bf16", 3e-2, (-1, -1), 12, 5)]
 
 
 def _iter_name(precision, tiles, k):
@@ -197,6 +202,14 @@ def _prepare(root):
     d = os.path.join(root, "serve")
     write_inputs(d, v["case"], v["w"], "f32", 1, mask=v["mask"], tiles=(0, 0), serve=True)
     runs["serve"] = d
+    d = os.path.join(root, "serve-bf16")
+    write_inputs(d, v["case"], v["w"], "bf16", 1, mask=v["mask"], tiles=(0, 0), serve=True)
+    runs["serve-bf16"] = d
+    for precision in ("bf16", "bf16x3"):
+        case, w = _iter_spec(5)
+        d = os.path.join(root, "refresh-" + precision)
+        write_inputs(d, case, w, precision, 1, tiles=(0, 0))
+        runs["refresh-" + precision] = d
     return runs
 
 
@@ -242,12 +255,41 @@ def test_emulated_iterations_match_oracle(emu, precision, tol, tiles, solve, k):
         got = rd(d, name + ".f64", ref.shape)
         print(precision, name, rel_err(got, ref))
         assert rel_err(got, ref) < tol, (name, rel_err(got, ref))
-    st2 = oadmm.admm_iterate(slp, rho, 1, st)
-    assert rel_err(rd(d, "z1b.f64", st2.z1.shape), st2.z1) < tol
+    if precision == "bf16":
+        # the state re-imported and one iteration: a chunk of one iteration is a
+        # refresh (pair products), so it follows the oracle's step from the
+        # exported state to the pair products' accuracy
+        got = oadmm.ADMMState(*(rd(d, nm + ".f64", ref.shape) for nm, ref in
+                                (("z1", st.z1), ("y1", st.y1), ("z2", st.z2), ("y2", st.y2))))
+        st2 = oadmm.admm_iterate(slp, rho, 1, got)
+        assert rel_err(rd(d, "z1b.f64", st2.z1.shape), st2.z1) < 2e-4
+    else:
+        st2 = oadmm.admm_iterate(slp, rho, 1, st)
+        assert rel_err(rd(d, "z1b.f64", st2.z1.shape), st2.z1) < tol
     t = rd(d, "t.f64", (k, lp.n_t))
     F = olp.planning_objective(case, w, t.T)[0]
-    res = rd(d, "res.f64", (5, k))
+    res = rd(d, "res.f64", (7, k))
     assert rel_err(res[0], F) < (1e-10 if precision == "f64" else 1e-5 if precision == "f32" else 2e-4)
+    # the device's certified bounds are the oracle's for the same iterate (the
+    # oracle's dual point from the exported z1, the same global BOT repair)
+    cert = olp.certify(case, w, t.T, rd(d, "z1.f64", st.z1.shape)[:case.n_points], lp=lp)
+    tol_c = 1e-10 if precision == "f64" else 1e-5 if precision == "f32" else 2e-4
+    assert rel_err(res[5], cert["L"]) < tol_c, (res[5], cert["L"])
+    assert np.max(np.abs(res[6] - cert["cert_gap"])) < 10 * tol_c, (res[6], cert["cert_gap"])
+
+
+def test_emulated_refresh_chunks_equal_pair_products(emu):
+    """LADMM_BF16 with every chunk one iteration long runs only refresh
+    iterations, whose products are the three-term pair products of
+    LADMM_BF16X3: the two modes give the same bits."""
+    a = finished(emu, "refresh-bf16")
+    b = finished(emu, "refresh-bf16x3")
+    case, w = _iter_spec(5)
+    n_A = case.n_points + case.n_iso * case.n_sectors
+    for name in ("z1", "y1", "z1b"):
+        x = rd(a, name + ".f64", (n_A, 5))
+        y = rd(b, name + ".f64", (n_A, 5))
+        assert np.array_equal(x, y), name
 
 
 def test_emulated_ld_mask_oar_band_and_alg1(emu):
@@ -310,13 +352,14 @@ def test_emulated_two_pass(emu, run, levels, passes):
     assert rel_err(rd(d, "tp_f2.f64", (k,)), F2) < 1e-10
 
 
-def test_emulated_serving(emu):
+@pytest.mark.parametrize("run", ["serve", "serve-bf16"])
+def test_emulated_serving(emu, run):
     """Continuous batching through ladmm_submit/wait/cancel: a cancelled request,
     then two requests whose plans share 32 slots (later plans start in slots
     freed by earlier ones).  Every plan's shot times, objective and iteration
     count equal those of ladmm_solve_batch on its own request, bitwise, and the
     objective is the oracle's F of the returned shot times."""
-    d = finished(emu, "serve")
+    d = finished(emu, run)
     v = _serve_spec()
     case, w, mask = v["case"], v["w"], v["mask"]
     k = w.shape[0]
@@ -335,7 +378,12 @@ def test_emulated_serving(emu):
     # warm starts: 2 iterations from the stored state of the same plans after 2
     # iterations equal 4 iterations from cold (up to the rounding of the
     # rebuilt W' columns)
+    # rebuilt W' columns).  In the BF16 refinement mode a warm-started column
+    # starts with zero references, so its first iteration multiplies the full
+    # operands as single BF16 values (2^-9 relative rounding each) before the
+    # refresh that ends the chunk.
     kk = 6
+    tol_f, tol_t = (1e-6, 1e-5) if run == "serve" else (2e-3, 2e-2)
     assert np.fromfile(os.path.join(d, "warm_i.i32"), np.int32).tolist() == [2] * kk
-    assert rel_err(rd(d, "warm_f.f64", (kk,)), rd(d, "cold2_f.f64", (kk,))) < 1e-6
-    assert rel_err(rd(d, "warm_t.f64", (kk, n_t)), rd(d, "cold2_t.f64", (kk, n_t))) < 1e-5
+    assert rel_err(rd(d, "warm_f.f64", (kk,)), rd(d, "cold2_f.f64", (kk,))) < tol_f
+    assert rel_err(rd(d, "warm_t.f64", (kk, n_t)), rd(d, "cold2_t.f64", (kk, n_t))) < tol_t
