@@ -775,6 +775,13 @@ BfPair plan_pairs(void *buf, int kp, int len) {
   return BfPair{h, h + (size_t)kp * len, len};
 }
 
+// Tile configuration of a three-term pair product (which: 0 split-K, 1
+// point-row): LADMM_BF16 keeps its own for the refresh and the checks.
+int cfg_pairs(const ladmm_batch *b, int which) {
+  if (b->c->precision == LADMM_BF16) return which == 0 ? b->cfg1r : b->cfg2r;
+  return which == 0 ? b->cfg1 : b->cfg2;
+}
+
 // The check after a pair-product iteration: the objective product of the
 // current shot times (pairs) and the per-plan statistics.
 int check_stats_bf(ladmm_batch *b, const EpiArgs<float> &ea) {
@@ -787,12 +794,12 @@ int check_stats_bf(ladmm_batch *b, const EpiArgs<float> &ea) {
   PROF(6, (shot_scaled_bf(s, sa, b->q2, (uint16_t *)Tt.hi, (uint16_t *)Tt.lo)));
   EpiArgs<float> eo = ea;
   eo.stats = b->obj_stats;
-  PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, b->cfg2)));
+  PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, cfg_pairs(b, 1))));
   // certificate: z1 of the new iterate (pairs) times the dose block
   const BfPair DT{c->DTh, c->DTl, c->Np};
   const BfPair Z = plan_pairs(b->zc, kp, c->Np);
   PROF(8, (z_from_q_bf(s, (const float *)b->q, c->Np, kp, ea.pt, (uint16_t *)Z.hi, (uint16_t *)Z.lo)));
-  PROF(8, (gemm_bf_tn(s, DT, Z, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+  PROF(8, (gemm_bf_tn(s, DT, Z, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, cfg_pairs(b, 0))));
   PROF(8, (cert_need<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->need)));
   FinalArgs fa;
   fa.admm_stats = b->admm_stats;
@@ -858,7 +865,7 @@ int iterate_bfr(ladmm_batch *b, int phase) {
   const BfPair dW{b->dW, nullptr, c->Np}, dV{V.hi, nullptr, c->ntp};
   SmallArgs sa = small_args(b);
   if (refresh)
-    PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+    PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1r)));
   else
     PROF(0, (gemm_bf_tn(s, DT, dW, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 1, b->cfg1)));
   PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r,
@@ -888,7 +895,7 @@ int iterate_bfr(ladmm_batch *b, int phase) {
   ea.wref = b->wref;
   ea.dw = b->dW;
   if (refresh)
-    PROF(10, (gemm_bf_nn(s, EPI_ADMM_STATS, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2, BF_REFRESH)));
+    PROF(10, (gemm_bf_nn(s, EPI_ADMM_STATS, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2r, BF_REFRESH)));
   else
     PROF(4, (gemm_bf_nn(s, EPI_ADMM, Dp, dV, c->Np, kp, c->ntp, ea, 1, b->cfg2, phase)));
   if (refresh) return check_stats_bf(b, ea);
@@ -917,23 +924,25 @@ void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np 
 // never the order of the sums, so the choice does not affect the iterates.
 // Whether tile configuration cfg suits the split-K (which = 0) or the
 // point-row (which = 1) product of this batch's shapes.
-bool cfg_ok(const ladmm_batch *b, int which, int cfg) {
+bool cfg_ok(const ladmm_batch *b, int which, int cfg, int terms) {
   const ladmm_case *c = b->c;
   if (bf16_block(c->precision))
-    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kp) : gemm_bf_cfg_ok(1, cfg, c->Np, b->kp);
+    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kp, terms)
+                      : gemm_bf_cfg_ok(1, cfg, c->Np, b->kp, terms);
   return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kp) : gemm_nn_cfg_ok(cfg, c->Np, b->kp);
 }
 
 // One launch of a dose-matrix product in configuration cfg (the point-row
 // product with its writes masked off by `noact`).
 template <typename T>
-hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact) {
+hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact, int terms) {
   ladmm_case *c = b->c;
   hipStream_t s = b->stream;
   const int kp = b->kp;
   if (bf16_block(c->precision)) {
-    // LADMM_BF16 times its hot iterations: single-operand products
-    const bool one = c->precision == LADMM_BF16;
+    // LADMM_BF16's hot iterations: single-operand products; its refresh and
+    // LADMM_BF16X3: pair products
+    const bool one = terms == 1;
     const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
     if (which == 0)
       return gemm_bf_tn(s, DT, one ? BfPair{b->dW, nullptr, c->Np} : plan_pairs(b->W, kp, c->Np),
@@ -984,6 +993,8 @@ int autotune(ladmm_batch *b) {
       b->cfg1 = e.cfg1;
       b->cfg2 = e.cfg2;
       b->cfg_s = e.cfg_s;
+      b->cfg1r = e.cfg1r;
+      b->cfg2r = e.cfg2r;
       b->tuned = true;
       set_row_blocks(b);
       return LADMM_OK;
@@ -993,22 +1004,28 @@ int autotune(ladmm_batch *b) {
   int32_t *noact = nullptr;
   HIPC(hipMalloc((void **)&noact, kp * sizeof(int32_t)));
   hipError_t e = hipMemsetAsync(noact, 0, kp * sizeof(int32_t), s);
-  float best1 = 1e30f, best2 = 1e30f;
-  for (int cfg = 0; cfg < kMaxGemmCfgs && e == hipSuccess; ++cfg) {
-    for (int which = 0; which < 2 && e == hipSuccess; ++which) {
-      if (!cfg_ok(b, which, cfg)) continue;
-      float tot = 0.f;
-      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-        e = hipEventRecord(b->ev0, s);
-        if (e == hipSuccess) e = tune_launch<T>(b, which, cfg, noact);
-        if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
-        if (rep > 0) tot += ms;     // the first launch warms caches
+  // the hot products; LADMM_BF16 also times its refresh's pair products
+  const int hot_terms = c->precision == LADMM_BF16 ? 1 : 3;
+  for (int pass = 0; pass < (c->precision == LADMM_BF16 ? 2 : 1) && e == hipSuccess; ++pass) {
+    const int terms = pass == 0 ? hot_terms : 3;
+    float best1 = 1e30f, best2 = 1e30f;
+    int *c1 = pass == 0 ? &b->cfg1 : &b->cfg1r, *c2 = pass == 0 ? &b->cfg2 : &b->cfg2r;
+    for (int cfg = 0; cfg < kMaxGemmCfgs && e == hipSuccess; ++cfg) {
+      for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+        if (!cfg_ok(b, which, cfg, terms)) continue;
+        float tot = 0.f;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(b->ev0, s);
+          if (e == hipSuccess) e = tune_launch<T>(b, which, cfg, noact, terms);
+          if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, b->ev0, b->ev1);
+          if (rep > 0) tot += ms;     // the first launch warms caches
+        }
+        if (which == 0 && tot < best1) { best1 = tot; *c1 = cfg; }
+        if (which == 1 && tot < best2) { best2 = tot; *c2 = cfg; }
       }
-      if (which == 0 && tot < best1) { best1 = tot; b->cfg1 = cfg; }
-      if (which == 1 && tot < best2) { best2 = tot; b->cfg2 = cfg; }
     }
   }
   hipFree(noact);
@@ -1032,7 +1049,7 @@ int autotune(ladmm_batch *b) {
     if (tot < best_s) { best_s = tot; b->cfg_s = cfg; }
   }
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-  c->tuned.push_back({kp, b->cfg1, b->cfg2, b->cfg_s});
+  c->tuned.push_back({kp, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r});
   b->tuned = true;
   set_row_blocks(b);
   return LADMM_OK;
@@ -1061,7 +1078,9 @@ int enqueue_iterations(ladmm_batch *b, int n) {
   }
   hipGraphExec_t exec = nullptr;
   for (const auto &g : b->graph_cache)
-    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2 && g.cfg_s == b->cfg_s) exec = g.exec;
+    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2 && g.cfg_s == b->cfg_s &&
+        g.cfg1r == b->cfg1r && g.cfg2r == b->cfg2r)
+      exec = g.exec;
   if (!exec) {
     if (!b->cap_stream) HIPC(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     // the launches below go to the capture stream; the graph runs on b->stream
@@ -1091,7 +1110,7 @@ int enqueue_iterations(ladmm_batch *b, int n) {
       hipGraphExecDestroy(b->graph_cache.front().exec);
       b->graph_cache.erase(b->graph_cache.begin());
     }
-    b->graph_cache.push_back({n, b->cfg1, b->cfg2, b->cfg_s, exec});
+    b->graph_cache.push_back({n, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r, exec});
   }
   HIPC(hipGraphLaunch(exec, b->stream));
   return LADMM_OK;
@@ -1521,8 +1540,13 @@ int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
   if (gemm1 < 0 || gemm1 >= kMaxGemmCfgs || gemm2 < 0 || gemm2 >= kMaxGemmCfgs)
     return fail(LADMM_E_INVALID, "tile configuration out of range");
-  b->cfg1 = cfg_ok(b, 0, gemm1) ? gemm1 : 0;
-  b->cfg2 = cfg_ok(b, 1, gemm2) ? gemm2 : 0;
+  // the refresh's pair products take the same configurations where they serve
+  // three terms, else configuration 0
+  b->cfg1r = cfg_ok(b, 0, gemm1, 3) ? gemm1 : 0;
+  b->cfg2r = cfg_ok(b, 1, gemm2, 3) ? gemm2 : 0;
+  const int terms = b->c->precision == LADMM_BF16 ? 1 : 3;
+  b->cfg1 = cfg_ok(b, 0, gemm1, terms) ? gemm1 : 0;
+  b->cfg2 = cfg_ok(b, 1, gemm2, terms) ? gemm2 : 0;
   b->tuned = true;
   set_row_blocks(b);
   return LADMM_OK;

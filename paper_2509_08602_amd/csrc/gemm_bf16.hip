@@ -114,14 +114,18 @@ template <int BM, int BN, int MODE>
 constexpr size_t bf_stat_bytes() { return bf_has_stats<MODE>() ? sizeof(double) * (BM / 16) * bf_nstat<MODE>() * BN : 0; }
 template <int BM>
 constexpr int bf_wstage_ld() { return BM + 8; }
-template <int MODE>
-constexpr bool bf_wstaged() { return MODE == EPI_ADMM; }
 template <int DL>
 constexpr int bf_wstage_halves() { return DL == BF_DELTA ? 1 : 2; }
+// Staged only where the staging fits beside the operand tiles' LDS (the widest
+// tiles write W' pairs directly).
+template <int BM, int BN, int MODE, int DL>
+constexpr bool bf_wstaged() {
+  return MODE == EPI_ADMM && bf_wstage_halves<DL>() * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() <= 128 * 1024;
+}
 template <int BM, int BN, int MODE, int DL>
 constexpr size_t bf_red_bytes() {
   return bf_stat_bytes<BM, BN, MODE>() +
-         (bf_wstaged<MODE>() ? bf_wstage_halves<DL>() * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
+         (bf_wstaged<BM, BN, MODE, DL>() ? bf_wstage_halves<DL>() * sizeof(uint16_t) * BN * bf_wstage_ld<BM>() : 0);
 }
 
 __device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
@@ -152,7 +156,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
   constexpr bool kPairsOut = DL != BF_DELTA;                          // W' as pairs
   constexpr bool kDwOut = DL == BF_DELTA || DL == BF_REFRESH;         // dW = bf16(W' - W_ref)
   static_assert(MODE != EPI_OBJ || DL == BF_PLAIN, "the objective product has no refinement variant");
-  static_assert(DL != BF_REFRESH || !bf_wstaged<MODE>(), "the refresh stores its outputs directly");
+  static_assert(DL != BF_REFRESH || !bf_wstaged<BM, BN, MODE, DL>(), "the refresh stores its outputs directly");
   static_assert(MODE != EPI_ADMM_STATS || DL == BF_PLAIN || DL == BF_REFRESH,
                 "statistics come from the pair products");
   const int lane = tid & 63, wave = tid >> 6;
@@ -269,7 +273,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           }
         }
       }
-      if (bf_wstaged<MODE>()) {
+      if (bf_wstaged<BM, BN, MODE, DL>()) {
         // staged: column n - n0, rows mb - m0 .. + 3
         const int cl = n - n0, rl = mb - m0;
         if (DL == BF_DELTA) {
@@ -278,10 +282,12 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(wh);
           *reinterpret_cast<uint2 *>(&swl[cl][rl]) = pack4(wl);
         }
-      } else if (MODE == EPI_ADMM_STATS && act[tn]) {
+      } else if (MODE != EPI_OBJ && act[tn]) {
         const size_t o = (size_t)n * ea.ldwt + mb;
-        *reinterpret_cast<uint2 *>(ea.wt_hi + o) = pack4(wh);
-        *reinterpret_cast<uint2 *>(ea.wt_lo + o) = pack4(wl);
+        if (kPairsOut) {
+          *reinterpret_cast<uint2 *>(ea.wt_hi + o) = pack4(wh);
+          *reinterpret_cast<uint2 *>(ea.wt_lo + o) = pack4(wl);
+        }
         if (kDwOut) *reinterpret_cast<uint2 *>(ea.dw + o) = pack4(dw);
       }
       if (kStats) {
@@ -301,7 +307,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
     }
   if (MODE == EPI_OBJ && !kStats) return;
   __syncthreads();
-  if (bf_wstaged<MODE>()) {
+  if (bf_wstaged<BM, BN, MODE, DL>()) {
     // W' (or dW) of the active plans: each column's BM rows as 16-byte pieces, in order
     for (int e = tid; e < BN * (BM / 8); e += NT) {
       const int cl = e / (BM / 8), ch = (e % (BM / 8)) * 8;
@@ -609,15 +615,22 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
 // product (1): rows BM x columns BN of a workgroup, staged (both operands
 // through LDS, k_gemm_bf) or direct (A from global memory, k_gemm_bfd).
 // Configuration 0 is valid for every padded shape (M % 64, N % 32).
-constexpr int kBfCfgCount = 6;
-struct BfCfg { int bm, bn; };
+// Configurations 6 and 7 are for single-operand products only (terms = 1):
+// a workgroup covers all 448 plan columns of a 441-plan batch (or 224), so the
+// dose block is read once per product; 8 (point-row) or 4 (split-K) waves
+// split rows and columns and share both operand tiles through LDS.
+constexpr int kBfCfgCount = 8;
+struct BfCfg { int bm, bn; bool single_only; };
 static const BfCfg kBfCfgs[2][kBfCfgCount] = {
-    {{64, 32}, {64, 64}, {192, 112}, {160, 112}, {64, 96}, {192, 64}},
-    {{64, 32}, {256, 64}, {128, 112}, {128, 112}, {128, 96}, {128, 64}}};
+    {{64, 32, false}, {64, 64, false}, {192, 112, false}, {160, 112, false}, {64, 96, false},
+     {192, 64, false}, {64, 448, true}, {64, 224, true}},
+    {{64, 32, false}, {256, 64, false}, {128, 112, false}, {128, 112, false}, {128, 96, false},
+     {128, 64, false}, {128, 448, true}, {128, 224, true}}};
 
-bool gemm_bf_cfg_ok(int which, int cfg, int M, int N) {
+bool gemm_bf_cfg_ok(int which, int cfg, int M, int N, int terms) {
   if (cfg < 0 || cfg >= kBfCfgCount) return false;
   const BfCfg c = kBfCfgs[which][cfg];
+  if (c.single_only && terms != 1) return false;
   return M % c.bm == 0 && N % c.bn == 0;
 }
 
@@ -642,6 +655,12 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 3: BF_DI(5, 7, 2); break;
       case 4: BF_DI(1, 6, 4); break;
       case 5: BF_DI(3, 4, 4); break;
+      case 6:
+        if constexpr (TERMS == 1) { BF_ST(64, 448, 1, 4, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 7:
+        if constexpr (TERMS == 1) { BF_ST(64, 224, 1, 2, 2); } else { return hipErrorInvalidValue; }
+        break;
       default: return hipErrorInvalidValue;
     }
   } else {
@@ -652,6 +671,12 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 3: BF_DI(4, 7, 2); break;
       case 4: BF_DI(2, 6, 4); break;
       case 5: BF_DI(2, 4, 4); break;
+      case 6:
+        if constexpr (TERMS == 1) { BF_ST(128, 448, 2, 4, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 7:
+        if constexpr (TERMS == 1) { BF_ST(128, 224, 2, 2, 2); } else { return hipErrorInvalidValue; }
+        break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -662,8 +687,8 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
 
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg) {
-  if (!gemm_bf_cfg_ok(0, cfg, M, N)) cfg = 0;
-  if (!gemm_bf_cfg_ok(0, cfg, M, N) || nchunk < 1 || K % 8 || A.ld % 8 || B.ld % 8)
+  if (!gemm_bf_cfg_ok(0, cfg, M, N, terms)) cfg = 0;
+  if (!gemm_bf_cfg_ok(0, cfg, M, N, terms) || nchunk < 1 || K % 8 || A.ld % 8 || B.ld % 8)
     return hipErrorInvalidValue;
   int kchunk = (K + nchunk - 1) / nchunk;
   kchunk = (kchunk + 31) / 32 * 32;
@@ -676,8 +701,8 @@ hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int 
 
 hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, int K,
                       const EpiArgs<float> &ea, int terms, int cfg, int delta) {
-  if (!gemm_bf_cfg_ok(1, cfg, M, N)) cfg = 0;
-  if (!gemm_bf_cfg_ok(1, cfg, M, N) || K % kBfBK || A.ld % 8 || B.ld % 8) return hipErrorInvalidValue;
+  if (!gemm_bf_cfg_ok(1, cfg, M, N, terms)) cfg = 0;
+  if (!gemm_bf_cfg_ok(1, cfg, M, N, terms) || K % kBfBK || A.ld % 8 || B.ld % 8) return hipErrorInvalidValue;
   // the combinations the iteration uses: pairs (three terms) for BF16X3, the
   // objective and the refresh; single operands for the hot iterations
 #define BF_EPI(E, T, D) return launch_bf<E, T, D>(cfg, M, N, 1, s, A, B, K, K, nullptr, 0, 0, ea)

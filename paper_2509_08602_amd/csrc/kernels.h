@@ -198,7 +198,8 @@ hipError_t import_points(hipStream_t s, T *q, int ldq, int N, int k, const doubl
 // a single BF16 operand on each side) on the BF16 MFMA with FP32
 // accumulation, in the same order for every tile configuration.
 struct BfPair { const uint16_t *hi, *lo; int ld; };
-bool gemm_bf_cfg_ok(int which, int cfg, int M, int N);   // which: 0 split-K, 1 point-row
+// which: 0 split-K, 1 point-row; some configurations serve terms = 1 only
+bool gemm_bf_cfg_ok(int which, int cfg, int M, int N, int terms);
 // P[z][m][n] = sum over rows k of chunk z of A[m][k] B[n][k]  (split-K partials, FP32)
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg);

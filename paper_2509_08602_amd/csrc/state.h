@@ -19,7 +19,7 @@ namespace ladmm {
 
 // Tile configurations per dose-matrix product in the largest table (the
 // BF16-pair kernels; the FP32 / FP64 tables have kGemmCfgs and reject the rest).
-constexpr int kMaxGemmCfgs = 6;
+constexpr int kMaxGemmCfgs = 8;
 
 // Message of the last error on the calling thread (ladmm_last_error).
 extern thread_local std::string g_err;
@@ -106,7 +106,7 @@ struct ladmm_case {
   int refs = 0;              // live batches
   bool destroyed = false;    // destroy requested while batches were alive
   // per padded plan count: tiles of GEMM1, GEMM2 and the S^-1 product
-  struct Tuned { int kp, cfg1, cfg2, cfg_s; };
+  struct Tuned { int kp, cfg1, cfg2, cfg_s, cfg1r, cfg2r; };
   std::vector<Tuned> tuned;
 };
 
@@ -155,11 +155,14 @@ struct ladmm_batch {
   int chunk_active = 0;       // active plans of the chunk in flight
   // tile configurations of the two dose-matrix products (autotuned)
   int cfg1 = 0, cfg2 = 0;
+  // LADMM_BF16: configurations of the refresh's three-term products (the
+  // widest single-operand tiles do not fit their LDS)
+  int cfg1r = 0, cfg2r = 0;
   int cfg_s = 1;              // the FP64 S^-1 r product (autotuned too)
   double alpha = 1.0;         // over-relaxation of the z- and y-steps
   bool tuned = false;
   // captured iteration chunks, replayed while profiling is off
-  struct Graph { int n, cfg1, cfg2, cfg_s; hipGraphExec_t exec; };
+  struct Graph { int n, cfg1, cfg2, cfg_s, cfg1r, cfg2r; hipGraphExec_t exec; };
   bool graphs = true;
   std::vector<Graph> graph_cache;
   // captures run on a stream of their own that does not synchronize with the

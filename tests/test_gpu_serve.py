@@ -116,8 +116,11 @@ def test_slot_reuse_and_masks_match_alone(ctx, mini, precision, eager):
         got = t.result()
         same(got, ref)
         assert np.all(got["iters"] == m)
+        # the objective product runs in FP32 (f32) or as BF16 pairs (16
+        # significant bits per operand, about 2^-16 relative per term)
         F = olp.planning_objective(mini, w[a:b], got["t"].T, mask[a:b])[0]
-        assert np.max(np.abs(got["objective"] - F) / np.maximum(np.abs(F), 1e-12)) < 1e-5
+        tol = 1e-5 if precision == "f32" else 5e-5
+        assert np.max(np.abs(got["objective"] - F) / np.maximum(np.abs(F), 1e-12)) < tol
     srv.close()
 
 

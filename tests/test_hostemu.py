@@ -121,7 +121,9 @@ ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
               # zero iterates the first changes are the full values, so the
               # iterates carry BF16 rounding (2^-9 relative per operand) until
               # the refresh that ends the chunk
-              ("bf16", 3e-2, (-1, -1), 12, 5)]
+              ("bf16", 3e-2, (-1, -1), 12, 5),
+              # the single-operand tiles that span 224 plan columns per workgroup
+              ("bf16", 3e-2, (7, 7), 0, 224)]
 
 
 def _iter_name(precision, tiles, k):
