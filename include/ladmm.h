@@ -280,6 +280,15 @@ int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2);
  * run the same kernels on the same arguments, so results are identical.
  * Profiling always launches one by one.  Graphs are destroyed with the batch. */
 int ladmm_batch_set_graphs(ladmm_batch *b, int32_t on);
+/* Compaction of the running plans (default on).  Between the checks of
+ * ladmm_batch_run (and ladmm_solve_batch), when plans have stopped, the
+ * running plans' columns (all their state) are moved to the lowest columns and
+ * the dose-matrix products launch only as many columns as they occupy (a
+ * multiple of 112 for the BF16 blocks, of 32 otherwise); the plans return to
+ * their own columns when the run ends.  A plan's arithmetic does not depend on
+ * its column, so results are identical with compaction on or off; only the
+ * work on stopped plans is saved. */
+int ladmm_batch_set_compaction(ladmm_batch *b, int32_t on);
 int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
 int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
 

@@ -569,8 +569,11 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   ladmm_batch *b = new ladmm_batch();
   b->c = c;
   b->kp = round_up(k, 32);
+  b->kact = b->kp;
   b->k = slots ? b->kp : k;
   k = b->k;
+  b->plan_at.resize(k);
+  for (int j = 0; j < k; ++j) b->plan_at[j] = j;
   b->opts = *opts;
   b->alpha = opts->alpha == 0.0 ? 1.0 : opts->alpha;
   if (slots)
@@ -628,6 +631,7 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
   B_RC(batch_alloc(b, &p, (size_t)c->n_iso * kp * sizeof(double))); b->bbot = (double *)p;
   B_RC(batch_alloc(b, &p, kp * sizeof(int32_t))); b->active = (int32_t *)p;
   B_RC(batch_alloc(b, &p, kp * sizeof(double))); b->fac = (double *)p;
+  B_RC(batch_alloc(b, &p, kp * sizeof(int32_t))); b->perm_d = (int *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk1 * c->ntp * kp * Tsz)); b->P1 = p;
   B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->r = (double *)p;
   B_RC(batch_alloc(b, &p, (size_t)c->nchunk2 * c->mAp * kp * sizeof(double))); b->P2 = (double *)p;
@@ -713,13 +717,13 @@ template <typename T>
 int iterate_once(ladmm_batch *b, bool stats) {
   ladmm_case *c = b->c;
   hipStream_t s = b->stream;
-  const int kp = b->kp;
+  const int kp = b->kp, kw = b->kact;   // leading dimension, launched columns
   PointTable<T> pt = point_table<T>(b);
   SmallArgs sa = small_args(b);
   PROF(0, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->W, kp, (T *)b->P1, kp, c->ntp,
-                      kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
+                      kw, c->Np, c->nchunk1, nullptr, b->cfg1)));
   PROF(1, (rhs<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
-  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kw, c->mAp,
                            c->nchunk2, nullptr, b->cfg_s)));
   PROF(3, (vreduce<T>(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (T *)b->vT)));
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, stats ? b->post_stats : nullptr, &b->post_blocks)));
@@ -734,18 +738,18 @@ int iterate_once(ladmm_batch *b, bool stats) {
   ea.pt = pt;
   ea.alpha = b->alpha;
   PROF(4, (gemm_nn<T>(s, stats ? EPI_ADMM_STATS : EPI_ADMM, (const T *)c->D, c->ntp,
-                      (const T *)b->vT, kp, c->Np, kp, c->ntp, ea, b->cfg2)));
+                      (const T *)b->vT, kp, c->Np, kw, c->ntp, ea, b->cfg2)));
   if (stats) {
     PROF(6, (shot_scaled<T>(s, sa, b->q2, (T *)b->that)));
     EpiArgs<T> eo = ea;
     eo.stats = b->obj_stats;
-    PROF(5, (gemm_nn<T>(s, EPI_OBJ, (const T *)c->D, c->ntp, (const T *)b->that, kp, c->Np, kp,
+    PROF(5, (gemm_nn<T>(s, EPI_OBJ, (const T *)c->D, c->ntp, (const T *)b->that, kp, c->Np, kw,
                         c->ntp, eo, b->cfg2)));
     // certificate: z1 of the new iterate times the dose block (the GEMM1
     // partials are free until the next iteration)
     PROF(8, (z_from_q<T>(s, (const T *)b->q, (T *)b->zc, c->Np, kp, pt)));
     PROF(8, (gemm_tn<T>(s, (const T *)c->D, c->ntp, (const T *)b->zc, kp, (T *)b->P1, kp, c->ntp,
-                        kp, c->Np, c->nchunk1, nullptr, b->cfg1)));
+                        kw, c->Np, c->nchunk1, nullptr, b->cfg1)));
     PROF(8, (cert_need<T>(s, sa, (const T *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->need)));
     FinalArgs fa;
     fa.admm_stats = b->admm_stats;
@@ -794,12 +798,13 @@ int check_stats_bf(ladmm_batch *b, const EpiArgs<float> &ea) {
   PROF(6, (shot_scaled_bf(s, sa, b->q2, (uint16_t *)Tt.hi, (uint16_t *)Tt.lo)));
   EpiArgs<float> eo = ea;
   eo.stats = b->obj_stats;
-  PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, kp, c->ntp, eo, 3, cfg_pairs(b, 1))));
+  PROF(5, (gemm_bf_nn(s, EPI_OBJ, Dp, Tt, c->Np, b->kact, c->ntp, eo, 3, cfg_pairs(b, 1))));
   // certificate: z1 of the new iterate (pairs) times the dose block
   const BfPair DT{c->DTh, c->DTl, c->Np};
   const BfPair Z = plan_pairs(b->zc, kp, c->Np);
   PROF(8, (z_from_q_bf(s, (const float *)b->q, c->Np, kp, ea.pt, (uint16_t *)Z.hi, (uint16_t *)Z.lo)));
-  PROF(8, (gemm_bf_tn(s, DT, Z, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, cfg_pairs(b, 0))));
+  PROF(8, (gemm_bf_tn(s, DT, Z, (float *)b->P1, kp, c->ntp, b->kact, c->Np, c->nchunk1, 3,
+                      cfg_pairs(b, 0))));
   PROF(8, (cert_need<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->need)));
   FinalArgs fa;
   fa.admm_stats = b->admm_stats;
@@ -829,9 +834,10 @@ int iterate_bf(ladmm_batch *b, bool stats) {
   const BfPair Dp{c->Dh, c->Dl, c->ntp}, DT{c->DTh, c->DTl, c->Np};
   const BfPair W = plan_pairs(b->W, kp, c->Np), V = plan_pairs(b->vT, kp, c->ntp);
   SmallArgs sa = small_args(b);
-  PROF(0, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1)));
+  const int kw = b->kact;
+  PROF(0, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kw, c->Np, c->nchunk1, 3, b->cfg1)));
   PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r)));
-  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kw, c->mAp,
                            c->nchunk2, nullptr, b->cfg_s)));
   PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
                       (uint16_t *)V.lo)));
@@ -848,7 +854,7 @@ int iterate_bf(ladmm_batch *b, bool stats) {
   ea.wt_lo = (uint16_t *)W.lo;
   ea.ldwt = c->Np;
   ea.alpha = b->alpha;
-  PROF(4, (gemm_bf_nn(s, stats ? EPI_ADMM_STATS : EPI_ADMM, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2)));
+  PROF(4, (gemm_bf_nn(s, stats ? EPI_ADMM_STATS : EPI_ADMM, Dp, V, c->Np, kw, c->ntp, ea, 3, b->cfg2)));
   if (stats) return check_stats_bf(b, ea);
   return LADMM_OK;
 }
@@ -864,13 +870,14 @@ int iterate_bfr(ladmm_batch *b, int phase) {
   const BfPair W = plan_pairs(b->W, kp, c->Np), V = plan_pairs(b->vT, kp, c->ntp);
   const BfPair dW{b->dW, nullptr, c->Np}, dV{V.hi, nullptr, c->ntp};
   SmallArgs sa = small_args(b);
+  const int kw = b->kact;
   if (refresh)
-    PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 3, b->cfg1r)));
+    PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kw, c->Np, c->nchunk1, 3, b->cfg1r)));
   else
-    PROF(0, (gemm_bf_tn(s, DT, dW, (float *)b->P1, kp, c->ntp, kp, c->Np, c->nchunk1, 1, b->cfg1)));
+    PROF(0, (gemm_bf_tn(s, DT, dW, (float *)b->P1, kp, c->ntp, kw, c->Np, c->nchunk1, 1, b->cfg1)));
   PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r,
                       refresh ? nullptr : b->gref, refresh ? b->gref : nullptr)));
-  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp,
+  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kw, c->mAp,
                            c->nchunk2, nullptr, b->cfg_s)));
   if (refresh)
     PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
@@ -895,9 +902,9 @@ int iterate_bfr(ladmm_batch *b, int phase) {
   ea.wref = b->wref;
   ea.dw = b->dW;
   if (refresh)
-    PROF(10, (gemm_bf_nn(s, EPI_ADMM_STATS, Dp, V, c->Np, kp, c->ntp, ea, 3, b->cfg2r, BF_REFRESH)));
+    PROF(10, (gemm_bf_nn(s, EPI_ADMM_STATS, Dp, V, c->Np, kw, c->ntp, ea, 3, b->cfg2r, BF_REFRESH)));
   else
-    PROF(4, (gemm_bf_nn(s, EPI_ADMM, Dp, dV, c->Np, kp, c->ntp, ea, 1, b->cfg2, phase)));
+    PROF(4, (gemm_bf_nn(s, EPI_ADMM, Dp, dV, c->Np, kw, c->ntp, ea, 1, b->cfg2, phase)));
   if (refresh) return check_stats_bf(b, ea);
   return LADMM_OK;
 }
@@ -927,9 +934,27 @@ void set_row_blocks(ladmm_batch *b) { b->admm_blocks = b->obj_blocks = b->c->Np 
 bool cfg_ok(const ladmm_batch *b, int which, int cfg, int terms) {
   const ladmm_case *c = b->c;
   if (bf16_block(c->precision))
-    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kp, terms)
-                      : gemm_bf_cfg_ok(1, cfg, c->Np, b->kp, terms);
-  return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kp) : gemm_nn_cfg_ok(cfg, c->Np, b->kp);
+    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kact, terms)
+                      : gemm_bf_cfg_ok(1, cfg, c->Np, b->kact, terms);
+  return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kact) : gemm_nn_cfg_ok(cfg, c->Np, b->kact);
+}
+
+// One launch of a dose-matrix product in configuration cfg (the point-row
+// product with its writes masked off by `noact`).
+template <typename T>
+// Pick the fastest tile configuration of each dose-matrix product for this
+// case and plan count: a few timed launches of every valid configuration on the
+// live batch (GEMM2 runs with its writes masked off).  Results are cached per
+// case and padded plan count.  The configurations change only the work split,
+// never the order of the sums, so the choice does not affect the iterates.
+// Whether tile configuration cfg suits the split-K (which = 0) or the
+// point-row (which = 1) product of this batch's shapes.
+bool cfg_ok(const ladmm_batch *b, int which, int cfg, int terms) {
+  const ladmm_case *c = b->c;
+  if (bf16_block(c->precision))
+    return which == 0 ? gemm_bf_cfg_ok(0, cfg, c->ntp, b->kact, terms)
+                      : gemm_bf_cfg_ok(1, cfg, c->Np, b->kact, terms);
+  return which == 0 ? gemm_tn_cfg_ok(cfg, c->ntp, b->kact) : gemm_nn_cfg_ok(cfg, c->Np, b->kact);
 }
 
 // One launch of a dose-matrix product in configuration cfg (the point-row
@@ -980,16 +1005,16 @@ hipError_t tune_launch(ladmm_batch *b, int which, int cfg, const int32_t *noact,
 }
 
 // Pick the fastest tile configuration of each dose-matrix product for this
-// case and plan count: a few timed launches of every valid configuration on the
-// live batch (the point-row product runs with its writes masked off).  Results
-// are cached per case and padded plan count.  The configurations change only
-// the work split, never the order of the sums, so the choice does not affect
-// the iterates.
+// case and launched width: a few timed launches of every valid configuration on
+// the live batch (the point-row product runs with its writes masked off).
+// Results are cached per case and launched width (the padded plan count, or a
+// compacted width).  The configurations change only the work split, never the
+// order of the sums, so the choice does not affect the iterates.
 template <typename T>
 int autotune(ladmm_batch *b) {
   ladmm_case *c = b->c;
   for (auto &e : c->tuned)
-    if (e.kp == b->kp) {
+    if (e.kp == b->kact) {
       b->cfg1 = e.cfg1;
       b->cfg2 = e.cfg2;
       b->cfg_s = e.cfg_s;
@@ -1033,13 +1058,13 @@ int autotune(ladmm_batch *b) {
   // the FP64 S^-1 r product (it writes only its split partials)
   float best_s = 1e30f;
   for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
-    if (!gemm_tn_cfg_ok(cfg, c->mAp, kp)) continue;
+    if (!gemm_tn_cfg_ok(cfg, c->mAp, b->kact)) continue;
     float tot = 0.f;
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
       e = hipEventRecord(b->ev0, s);
       if (e == hipSuccess)
-        e = gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kp, c->mAp, c->nchunk2,
-                            nullptr, cfg);
+        e = gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, b->kact, c->mAp,
+                            c->nchunk2, nullptr, cfg);
       if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
       if (e == hipSuccess) e = hipEventSynchronize(b->ev1);
       float ms = 0.f;
@@ -1049,7 +1074,7 @@ int autotune(ladmm_batch *b) {
     if (tot < best_s) { best_s = tot; b->cfg_s = cfg; }
   }
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-  c->tuned.push_back({kp, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r});
+  c->tuned.push_back({b->kact, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r});
   b->tuned = true;
   set_row_blocks(b);
   return LADMM_OK;
@@ -1078,8 +1103,8 @@ int enqueue_iterations(ladmm_batch *b, int n) {
   }
   hipGraphExec_t exec = nullptr;
   for (const auto &g : b->graph_cache)
-    if (g.n == n && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2 && g.cfg_s == b->cfg_s &&
-        g.cfg1r == b->cfg1r && g.cfg2r == b->cfg2r)
+    if (g.n == n && g.kact == b->kact && g.cfg1 == b->cfg1 && g.cfg2 == b->cfg2 &&
+        g.cfg_s == b->cfg_s && g.cfg1r == b->cfg1r && g.cfg2r == b->cfg2r)
       exec = g.exec;
   if (!exec) {
     if (!b->cap_stream) HIPC(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
@@ -1104,13 +1129,13 @@ int enqueue_iterations(ladmm_batch *b, int n) {
     }
     if (graph) hipGraphDestroy(graph);
     if (rc) return rc;
-    // a handful of chunk lengths per batch at most (the check interval and a
-    // shorter last chunk); keep the four most recent
-    if (b->graph_cache.size() == 4) {
+    // a handful of chunk lengths and compacted widths per batch; keep the
+    // eight most recent
+    if (b->graph_cache.size() == 8) {
       hipGraphExecDestroy(b->graph_cache.front().exec);
       b->graph_cache.erase(b->graph_cache.begin());
     }
-    b->graph_cache.push_back({n, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r, exec});
+    b->graph_cache.push_back({n, b->kact, b->cfg1, b->cfg2, b->cfg_s, b->cfg1r, b->cfg2r, exec});
   }
   HIPC(hipGraphLaunch(exec, b->stream));
   return LADMM_OK;
@@ -1206,6 +1231,136 @@ int adapt_rho(ladmm_batch *b, bool *switched) {
   return LADMM_OK;
 }
 
+// Permute the plan columns of a batch: column c takes the plan held in column
+// src[c] (src is a permutation of [0, k); padding columns stay), with all of
+// its device state (iterates, references of the refinement, bounds, step
+// sizes, masks) and host records.  Every kernel computes a plan's column from
+// that column's data only, in an order that does not depend on the column, so
+// a plan's arithmetic is the same in any column.
+int permute_columns(ladmm_batch *b, const std::vector<int> &src_k) {
+  ladmm_case *c = b->c;
+  hipStream_t s = b->stream;
+  const int kp = b->kp, k = b->k;
+  std::vector<int> src(kp);
+  for (int j = 0; j < kp; ++j) src[j] = j < k ? src_k[j] : j;
+  const size_t Tsz = c->precision == LADMM_F64 ? sizeof(double) : sizeof(float);
+  // arrays: (pointer, rows, element bytes, plan-major rows?)
+  struct Arr { void *p; size_t rows; int bytes; bool plan_rows; };
+  std::vector<Arr> arrs = {
+      {b->q, (size_t)c->Np, (int)Tsz, false},
+      {b->qs, (size_t)c->n_sec, 8, false},
+      {b->q2, (size_t)c->mAp, 8, false},
+      {b->utab, (size_t)(c->G + 1), (int)Tsz, false},
+      {b->invrho, 1, 8, false},
+      {b->wbot, 1, 8, false},
+      {b->bbot, (size_t)c->n_iso, 8, false},
+      {b->active, 1, 4, false}};
+  if (bf16_block(c->precision)) {
+    // W' pairs: kp hi rows, then kp lo rows, of Np values each
+    arrs.push_back({b->W, (size_t)c->Np, 2, true});
+    arrs.push_back({(uint16_t *)b->W + (size_t)kp * c->Np, (size_t)c->Np, 2, true});
+  } else {
+    arrs.push_back({b->W, (size_t)c->Np, (int)Tsz, false});
+  }
+  if (c->precision == LADMM_BF16) {
+    arrs.push_back({b->xref, (size_t)c->Np, 4, false});
+    arrs.push_back({b->wref, (size_t)c->Np, 4, false});
+    arrs.push_back({b->gref, (size_t)c->ntp, 8, false});
+    arrs.push_back({b->vref, (size_t)c->ntp, 8, false});
+    arrs.push_back({b->dW, (size_t)c->Np, 2, true});
+  }
+  if (b->mask) arrs.push_back({b->mask, (size_t)b->mask_words, 8, true});
+  size_t need = 0;
+  for (const Arr &a : arrs) need = std::max(need, a.rows * (size_t)kp * a.bytes);
+  if (need > b->perm_tmp_bytes) {
+    void *p = nullptr;
+    int rc = batch_alloc(b, &p, need);
+    if (rc) return rc;
+    b->perm_tmp = p;
+    b->perm_tmp_bytes = need;
+  }
+  HIPC(hipMemcpyAsync(b->perm_d, src.data(), kp * sizeof(int), hipMemcpyHostToDevice, s));
+  for (const Arr &a : arrs) {
+    const size_t bytes = a.rows * (size_t)kp * a.bytes;
+    if (a.plan_rows)
+      HIPC(gather_rows(s, a.p, b->perm_tmp, kp, a.rows, a.bytes, b->perm_d));
+    else
+      HIPC(gather_cols(s, a.p, b->perm_tmp, a.rows, kp, a.bytes, b->perm_d));
+    HIPC(hipMemcpyAsync(a.p, b->perm_tmp, bytes, hipMemcpyDeviceToDevice, s));
+  }
+  HIPC(hipStreamSynchronize(s));
+  // host records of the columns
+  auto perm = [&](auto &v) {
+    auto old = v;
+    for (int j = 0; j < k; ++j) v[j] = old[src[j]];
+  };
+  perm(b->w);
+  perm(b->rho);
+  perm(b->status);
+  perm(b->iters);
+  perm(b->start);
+  perm(b->rule);
+  perm(b->plan_at);
+  {
+    std::vector<int32_t> old(b->h_active.begin(), b->h_active.begin() + k);
+    for (int j = 0; j < k; ++j) b->h_active[j] = old[src[j]];
+  }
+  {
+    std::vector<double> old = b->rec;
+    for (int j = 0; j < k; ++j)
+      std::memcpy(&b->rec[(size_t)j * kFinal], &old[(size_t)src[j] * kFinal], kFinal * sizeof(double));
+  }
+  return LADMM_OK;
+}
+
+// Launched width for n running plans: the smallest multiple of the width unit
+// that holds them (BF16 blocks: 112 columns, the tiles of their tuned
+// configurations; FP32/FP64: 32), never above kp.
+int launch_width(const ladmm_batch *b, int n) {
+  const int unit = bf16_block(b->c->precision) ? 112 : 32;
+  return std::min(b->kp, std::max(unit, round_up(n, unit)));
+}
+
+// Between check chunks of a run: move the running plans to the lowest columns
+// when that lets the dose-matrix products launch fewer columns.
+int compact(ladmm_batch *b) {
+  const int k = b->k;
+  int n = 0;
+  for (int j = 0; j < k; ++j) n += b->h_active[j] != 0;
+  if (n == 0) return LADMM_OK;
+  const int w = launch_width(b, n);
+  if (w >= b->kact) return LADMM_OK;
+  std::vector<int> src;
+  src.reserve(k);
+  for (int j = 0; j < k; ++j)
+    if (b->h_active[j]) src.push_back(j);
+  for (int j = 0; j < k; ++j)
+    if (!b->h_active[j]) src.push_back(j);
+  int rc = permute_columns(b, src);
+  if (rc) return rc;
+  b->kact = w;
+  if (b->opts.autotune) b->tuned = false;   // tile configurations for the new width (cached)
+  return LADMM_OK;
+}
+
+// After a run: every plan back in its own column, all columns launched.
+int uncompact(ladmm_batch *b) {
+  const int k = b->k;
+  bool ident = true;
+  for (int j = 0; j < k; ++j) ident &= b->plan_at[j] == j;
+  if (!ident) {
+    std::vector<int> src(k);
+    for (int j = 0; j < k; ++j) src[b->plan_at[j]] = j;
+    int rc = permute_columns(b, src);
+    if (rc) return rc;
+  }
+  if (b->kact != b->kp) {
+    b->kact = b->kp;
+    if (b->opts.autotune) b->tuned = false;
+  }
+  return LADMM_OK;
+}
+
 // Run n iterations (the last one with statistics), update the host records and,
 // if `decide`, freeze plans that meet their stopping rule and, after a full
 // check chunk, balance the step sizes of the plans that ask for it.
@@ -1237,7 +1392,13 @@ int run_impl(ladmm_batch *b) {
     const int n = std::min(every, b->opts.max_iter - b->iters_run);
     int rc = run_chunk(b, n, true);
     if (rc) return rc;
+    if (b->compact) {
+      rc = compact(b);
+      if (rc) return rc;
+    }
   }
+  int rc = uncompact(b);
+  if (rc) return rc;
   for (int j = 0; j < b->k; ++j)
     if (b->status[j] == LADMM_PLAN_RUNNING) b->status[j] = LADMM_PLAN_MAX_ITER;
   return LADMM_OK;
@@ -1500,6 +1661,12 @@ int ladmm_batch_import(ladmm_batch *b, const double *z1, const double *y1, const
 int ladmm_batch_set_graphs(ladmm_batch *b, int32_t on) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
   b->graphs = on != 0;
+  return LADMM_OK;
+}
+
+int ladmm_batch_set_compaction(ladmm_batch *b, int32_t on) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  b->compact = on != 0;
   return LADMM_OK;
 }
 

@@ -241,14 +241,17 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
           float wref = 0.f;
           if (DL == BF_DELTA) wref = wr4[r];
           if (DL == BF_REFRESH) {
-            // the references of every column (frozen ones too: they stay
-            // consistent with q, which the refresh leaves unchanged there)
+            // the references of the running plans (a frozen plan keeps those
+            // of its last refresh, consistent with its G_ref and v_ref, which
+            // are recorded for running plans only too)
             uint16_t h, l;
             split_pair((double)(2.f * z - qv), h, l);   // the pairs the refresh's GEMM1 read
             wref = pair_val(h, l);
-            const size_t o = (size_t)m * ea.ldq + n;
-            ea.xref[o] = s;
-            ea.wref[o] = wref;
+            if (act[tn]) {
+              const size_t o = (size_t)m * ea.ldq + n;
+              ea.xref[o] = s;
+              ea.wref[o] = wref;
+            }
           }
           const float qx = z + sg * irc[tn] - s;   // x + y of the closed-form x-step
           // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
@@ -801,7 +804,7 @@ __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t 
     split_pair(acc, h, l);
     vh[(size_t)j * a.L.ntp + m] = h;
     vl[(size_t)j * a.L.ntp + m] = l;
-    if (vref != nullptr) vref[idx] = (double)pair_val(h, l);
+    if (vref != nullptr && a.active[j]) vref[idx] = (double)pair_val(h, l);
   }
 }
 

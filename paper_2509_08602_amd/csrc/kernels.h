@@ -106,7 +106,8 @@ struct SmallArgs {
 // r = A_s W + g / rho - (2 clip(q2) - q2), from the GEMM1 partials.  The
 // dose-point part G = sum of the partials; with gref (the BF16 refinement's hot
 // iterations) G = gref + partials (the product of the change since the last
-// refresh), and with gout (its refresh) G is also stored there.
+// refresh), and with gout (its refresh) G is also stored there for the
+// running plans.
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
                const double *qs, const double *q2, double *r, const double *gref = nullptr,
@@ -222,7 +223,8 @@ hipError_t gemm_bf_nn(hipStream_t s, int epi, BfPair A, BfPair B, int M, int N, 
 hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int Np, int ntp,
                            uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl);
 // v_top and the scaled shot times as plan-major pairs (kp x ntp) for the products.
-// With vref != NULL (a refresh): also vref := hi + lo (the value the pairs carry).
+// With vref != NULL (a refresh): also vref := hi + lo (the value the pairs
+// carry) for the running plans.
 hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
                       double *v, uint16_t *vh, uint16_t *vl, double *vref = nullptr);
 // v and dv = bf16(v_top - vref) plan-major (kp x ntp): the hot iterations of LADMM_BF16.
@@ -242,6 +244,14 @@ hipError_t zero_plan_rows_bf(hipStream_t s, uint16_t *a, int kp, int len, const 
 hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
                        uint16_t *wh, uint16_t *wl, const float *wref = nullptr,
                        uint16_t *dw = nullptr);
+
+// Permutations of plan columns (bytes = element size: 2, 4 or 8).
+// gather_cols: out[r][c] = in[r][src[c]] for a row-major rows x ld array;
+// gather_rows: out[r][:] = in[src[r]][:] for nrows rows of len elements.
+hipError_t gather_cols(hipStream_t s, const void *in, void *out, size_t rows, int ld, int bytes,
+                       const int *src);
+hipError_t gather_rows(hipStream_t s, const void *in, void *out, int nrows, size_t len, int bytes,
+                       const int *src);
 
 // Zero the columns j of a (rows x ld, row-major) whose flag[j] is nonzero:
 // the start of a fresh plan in a reused column.

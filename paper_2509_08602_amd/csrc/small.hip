@@ -340,7 +340,7 @@ __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int
     // the partials are independent loads: keep several in flight
 #pragma unroll 8
     for (int z = 0; z < nchunk; ++z) g += (double)P1[z * zstride + (size_t)m * kp + j];
-    if (gout != nullptr) gout[(size_t)m * kp + j] = g;
+    if (gout != nullptr && a.active[j]) gout[(size_t)m * kp + j] = g;
     if (gref != nullptr) g += gref[(size_t)m * kp + j];
     const int sec = m / L.C;
     const double qsv = qs[(size_t)sec * kp + j];
@@ -780,6 +780,63 @@ template hipError_t export_points<float>(hipStream_t, const float *, int, const 
 template hipError_t export_points<double>(hipStream_t, const double *, int, const PointTable<double> &, int, int, double *, double *);
 template hipError_t import_points<float>(hipStream_t, float *, int, int, int, const double *, const double *);
 template hipError_t import_points<double>(hipStream_t, double *, int, int, int, const double *, const double *);
+
+// ---------------------------------------------------------------------------
+// permutations of plan columns (compaction of the running plans)
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ void k_gather_cols(const E *__restrict__ in, E *__restrict__ out, size_t rows, int ld,
+                              const int *__restrict__ src) {
+  const size_t total = rows * (size_t)ld;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / ld;
+    out[e] = in[r * ld + src[e % ld]];
+  }
+}
+
+template <typename E>
+__global__ void k_gather_rows(const E *__restrict__ in, E *__restrict__ out, int nrows, size_t len,
+                              const int *__restrict__ src) {
+  const size_t total = (size_t)nrows * len;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / len;
+    out[e] = in[(size_t)src[r] * len + e % len];
+  }
+}
+
+static unsigned gather_blocks(size_t total) {
+  return (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+}
+
+hipError_t gather_cols(hipStream_t s, const void *in, void *out, size_t rows, int ld, int bytes,
+                       const int *src) {
+  const size_t total = rows * (size_t)ld;
+  if (total == 0) return hipSuccess;
+  const dim3 g(gather_blocks(total)), t(256);
+  switch (bytes) {
+    case 2: hipLaunchKernelGGL(k_gather_cols<uint16_t>, g, t, 0, s, (const uint16_t *)in, (uint16_t *)out, rows, ld, src); break;
+    case 4: hipLaunchKernelGGL(k_gather_cols<uint32_t>, g, t, 0, s, (const uint32_t *)in, (uint32_t *)out, rows, ld, src); break;
+    case 8: hipLaunchKernelGGL(k_gather_cols<uint64_t>, g, t, 0, s, (const uint64_t *)in, (uint64_t *)out, rows, ld, src); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gather_rows(hipStream_t s, const void *in, void *out, int nrows, size_t len, int bytes,
+                       const int *src) {
+  const size_t total = (size_t)nrows * len;
+  if (total == 0) return hipSuccess;
+  const dim3 g(gather_blocks(total)), t(256);
+  switch (bytes) {
+    case 2: hipLaunchKernelGGL(k_gather_rows<uint16_t>, g, t, 0, s, (const uint16_t *)in, (uint16_t *)out, nrows, len, src); break;
+    case 4: hipLaunchKernelGGL(k_gather_rows<uint32_t>, g, t, 0, s, (const uint32_t *)in, (uint32_t *)out, nrows, len, src); break;
+    case 8: hipLaunchKernelGGL(k_gather_rows<uint64_t>, g, t, 0, s, (const uint64_t *)in, (uint64_t *)out, nrows, len, src); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 // a[r][j] = 0 for every row r < rows and column j < ld with flag[j] != 0.
 template <typename T>

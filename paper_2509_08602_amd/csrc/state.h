@@ -113,6 +113,16 @@ struct ladmm_case {
 struct ladmm_batch {
   ladmm_case *c = nullptr;
   int k = 0, kp = 0, mask_words = 0;
+  // Launched plan columns of the dose-matrix products: kp, or (while
+  // ladmm_batch_run compacts the running plans into a dense prefix) fewer.
+  int kact = 0;
+  // Compaction state: plan held by each column (identity outside a run), and
+  // device scratch for the column permutation.
+  std::vector<int> plan_at;
+  int *perm_d = nullptr;
+  void *perm_tmp = nullptr;
+  size_t perm_tmp_bytes = 0;
+  bool compact = true;
   hipStream_t stream = nullptr;
   void *q = nullptr;          // Np x kp (T): q = z1 + y1 of the dose points
   void *W = nullptr;          // Np x kp (T): W = z1 - y1, input of the next GEMM1
@@ -162,7 +172,7 @@ struct ladmm_batch {
   double alpha = 1.0;         // over-relaxation of the z- and y-steps
   bool tuned = false;
   // captured iteration chunks, replayed while profiling is off
-  struct Graph { int n, cfg1, cfg2, cfg_s, cfg1r, cfg2r; hipGraphExec_t exec; };
+  struct Graph { int n, kact, cfg1, cfg2, cfg_s, cfg1r, cfg2r; hipGraphExec_t exec; };
   bool graphs = true;
   std::vector<Graph> graph_cache;
   // captures run on a stream of their own that does not synchronize with the

@@ -128,6 +128,7 @@ _SIGS = {
     "ladmm_batch_import": (C.c_int, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_batch_step_sizes": (C.c_int, [C.c_void_p, _DP]),
+    "ladmm_batch_set_compaction": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_metrics": (C.c_int, [C.c_void_p, C.c_int64, _DP, _IP, C.c_int32, _DP, C.c_double,
                                       _DP]),
@@ -379,6 +380,9 @@ class Batch:
         pit = C.c_int64()
         _check(library().ladmm_batch_timing(self._h, C.byref(ms), C.byref(pit)))
         return ms.value, pit.value
+
+    def set_compaction(self, on: bool):
+        _check(library().ladmm_batch_set_compaction(self._h, 1 if on else 0))
 
     def step_sizes(self):
         rho = np.empty(self.k)

@@ -43,11 +43,11 @@ int main(int argc, char **argv) {
   const std::string dir = argv[1];
   std::ifstream meta(dir + "/meta.txt");
   int N, n_iso, S, C, G, precision, k, iters, use_mask, n_vols, n_vox, band_vox, solve_iters;
-  int tile1 = -1, tile2 = -1, run_two_pass = 0, serve = 0;
+  int tile1 = -1, tile2 = -1, run_two_pass = 0, serve = 0, compact_iters = 0;
   double rho0, w0, D_T, phi_cal, d_ld, delta;
   unsigned long long seed;
   meta >> N >> n_iso >> S >> C >> G >> precision >> k >> iters >> rho0 >> w0 >> D_T >> phi_cal >>
-      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2 >> run_two_pass >> serve;
+      use_mask >> n_vols >> n_vox >> seed >> band_vox >> d_ld >> delta >> solve_iters >> tile1 >> tile2 >> run_two_pass >> serve >> compact_iters;
   const int n_t = n_iso * S * C, m_A = n_t + n_iso, n_A = N + n_iso * S;
   auto dose = load<double>(dir + "/dose.f64", (size_t)N * n_t);
   auto grp = load<int32_t>(dir + "/group.i32", N);
@@ -116,6 +116,26 @@ int main(int argc, char **argv) {
     so.max_iter = solve_iters; so.check_every = 5; so.tol_gap = 1e-6; so.tol_pri = 1e-6; so.tol_dual = 1e-6;
     so.adapt_rho = 1; so.adapt_mu = 1.5; so.adapt_tau = 2.0;   // step-size switches at every check
     CHECK(ladmm_solve_batch(cs, k, w.data(), use_mask ? mask.data() : nullptr, &so, &r));
+  }
+  if (compact_iters > 0) {
+    // plans that stop at different checks, run with compaction on and off
+    ladmm_opts co = o;
+    co.max_iter = compact_iters; co.check_every = 2; co.tol_gap = 0.2; co.tol_pri = 0; co.tol_dual = 0;
+    co.autotune = 1;
+    for (int on = 1; on >= 0; --on) {
+      ladmm_batch *cb = nullptr;
+      CHECK(ladmm_batch_create(cs, k, w.data(), use_mask ? mask.data() : nullptr, nullptr, &co, &cb));
+      CHECK(ladmm_batch_set_compaction(cb, on));
+      CHECK(ladmm_batch_run(cb));
+      CHECK(ladmm_batch_results(cb, &r));
+      const std::string tag = on ? "on" : "off";
+      save(dir + "/compact_t_" + tag + ".f64", t.data(), t.size());
+      save(dir + "/compact_res_" + tag + ".f64", res.data(), res.size());
+      save(dir + "/compact_it_" + tag + ".i32", it.data(), it.size());
+      CHECK(ladmm_batch_export(cb, z1.data(), y1.data(), z2.data(), y2.data()));
+      save(dir + "/compact_z1_" + tag + ".f64", z1.data(), z1.size());
+      CHECK(ladmm_batch_destroy(cb));
+    }
   }
   }
   if (n_vols > 0) {

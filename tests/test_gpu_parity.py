@@ -478,3 +478,32 @@ def test_refinement_refresh_step_matches_oracle_c1(ctx, c1):
         err = rel_err(g, ref)
         say(f"  {name}: err {err:.3e}, change over the chunk {change:.3e}")
         assert err < 2e-3 + 5 * 2.0 ** -8 * change, f"{name} rel err {err:.3e} (change {change:.3e})"
+
+
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_compaction_gives_identical_results(ctx, c0, precision):
+    """441 plans on the small case, stopping at different checks: a run that
+    compacts the running plans into the lowest columns (launching fewer
+    columns) gives every plan the same bits as a run that does not."""
+    say("compaction on/off c0", precision)
+    w = cases.config_weights(2)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    opts = ladmm.Options(max_iter=3000, check_every=50, tol_gap=1e-3, tol_pri=1e-3, tol_dual=1e-3,
+                         rho0=1e4, w0_bot=cases.W0_BOT, adapt_rho=True)
+    out = {}
+    for on in (True, False):
+        b = ladmm.Batch(dc, w, opts=opts)
+        b.set_compaction(on)
+        b.run()
+        out[on] = (b.results(), b.export(), b.step_sizes(), b.timing())
+        b.close()
+    ra, ea, rhoa, ta = out[True]
+    rb, eb, rhob, tb = out[False]
+    say("  iterations: distinct", len(set(ra["iters"].tolist())), "max", ra["iters"].max(),
+        "device ms with / without compaction", round(ta[0], 1), round(tb[0], 1))
+    assert len(set(ra["iters"].tolist())) > 3
+    for key in ra:
+        assert np.array_equal(ra[key], rb[key], equal_nan=True), key
+    for x, y in zip(ea, eb):
+        assert np.array_equal(x, y)
+    assert np.array_equal(rhoa, rhob)

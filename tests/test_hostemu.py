@@ -70,7 +70,7 @@ PRECISION = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
 
 def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, seed=0,
                  vox=None, d_ld=0.0, delta=1.0, solve_iters=0, rho0=1000.0, tiles=(-1, -1),
-                 two_pass=False, serve=False):
+                 two_pass=False, serve=False, compact_iters=0):
     os.makedirs(d, exist_ok=True)
     k = w.shape[0]
     n_vols = 0 if vols is None else vols.shape[0]
@@ -81,7 +81,7 @@ def write_inputs(d, case, w, precision, iters, mask=None, vols=None, n_ld=None, 
                 f"{len(case.groups)} {PRECISION[precision]} {k} {iters} {rho0!r} "
                 f"{cases.W0_BOT!r} {case.prescription_mean!r} {case.phi_cal!r} "
                 f"{0 if mask is None else 1} {n_vols} {n_vox} {seed} {band} {d_ld!r} {delta!r} "
-                f"{solve_iters} {tiles[0]} {tiles[1]} {int(two_pass)} {int(serve)}\n")
+                f"{solve_iters} {tiles[0]} {tiles[1]} {int(two_pass)} {int(serve)} {compact_iters}\n")
     np.ascontiguousarray(case.dose, np.float64).tofile(os.path.join(d, "dose.f64"))
     np.ascontiguousarray(case.group, np.int32).tofile(os.path.join(d, "group.i32"))
     with open(os.path.join(d, "groups.txt"), "w") as f:
@@ -124,6 +124,11 @@ ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
               ("bf16", 3e-2, (-1, -1), 12, 5),
               # the single-operand tiles that span 224 plan columns per workgroup
               ("bf16", 3e-2, (7, 7), 0, 224)]
+
+
+# compaction runs: enough plans for the launched width to shrink (FP32 in
+# 32-column steps, BF16 in 112-column steps)
+COMPACT_CASES = [("f32", 70), ("bf16", 120)]
 
 
 def _iter_name(precision, tiles, k):
@@ -212,6 +217,11 @@ def _prepare(root):
         d = os.path.join(root, "refresh-" + precision)
         write_inputs(d, case, w, precision, 1, tiles=(0, 0))
         runs["refresh-" + precision] = d
+    for precision, k in COMPACT_CASES:
+        case, w = _iter_spec(k)
+        d = os.path.join(root, f"compact-{precision}")
+        write_inputs(d, case, w, precision, 1, tiles=(0, 0), compact_iters=8)
+        runs[f"compact-{precision}"] = d
     return runs
 
 
@@ -389,3 +399,21 @@ def test_emulated_serving(emu, run):
     assert np.fromfile(os.path.join(d, "warm_i.i32"), np.int32).tolist() == [2] * kk
     assert rel_err(rd(d, "warm_f.f64", (kk,)), rd(d, "cold2_f.f64", (kk,))) < tol_f
     assert rel_err(rd(d, "warm_t.f64", (kk, n_t)), rd(d, "cold2_t.f64", (kk, n_t))) < tol_t
+
+
+@pytest.mark.parametrize("precision,k", COMPACT_CASES)
+def test_emulated_compaction_gives_identical_results(emu, precision, k):
+    """ladmm_batch_run with the running plans compacted into the lowest columns
+    between checks, and without: the same bits for every plan, and plans that
+    stopped at different checks."""
+    d = finished(emu, f"compact-{precision}")
+    case, w = _iter_spec(k)
+    n_A = case.n_points + case.n_iso * case.n_sectors
+    it_on = np.fromfile(os.path.join(d, "compact_it_on.i32"), np.int32)
+    it_off = np.fromfile(os.path.join(d, "compact_it_off.i32"), np.int32)
+    assert np.array_equal(it_on, it_off)
+    assert len(set(it_on.tolist())) > 1, it_on     # plans stopped at different checks
+    for name, shape in (("compact_t", (k, case.n_t)), ("compact_res", (7, k)), ("compact_z1", (n_A, k))):
+        a = rd(d, name + "_on.f64", shape)
+        b = rd(d, name + "_off.f64", shape)
+        assert np.array_equal(a, b, equal_nan=True), name
