@@ -284,7 +284,8 @@ int ladmm_batch_set_graphs(ladmm_batch *b, int32_t on);
  * ladmm_batch_run (and ladmm_solve_batch), when plans have stopped, the
  * running plans' columns (all their state) are moved to the lowest columns and
  * the dose-matrix products launch only as many columns as they occupy (a
- * multiple of 112 for the BF16 blocks, of 32 otherwise); the plans return to
+ * multiple of 32; for the BF16 blocks one that admits a tile of 64, 96 or 224
+ * columns); the plans return to
  * their own columns when the run ends.  A plan's arithmetic does not depend on
  * its column, so results are identical with compaction on or off; only the
  * work on stopped plans is saved. */

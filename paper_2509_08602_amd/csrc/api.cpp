@@ -1313,12 +1313,15 @@ int permute_columns(ladmm_batch *b, const std::vector<int> &src_k) {
   return LADMM_OK;
 }
 
-// Launched width for n running plans: the smallest multiple of the width unit
-// that holds them (BF16 blocks: 112 columns, the tiles of their tuned
-// configurations; FP32/FP64: 32), never above kp.
+// Launched width for n running plans: the smallest multiple of 32 (every
+// product's column granule) that holds them and, for the BF16 blocks, also
+// admits one of their wider column tiles (64, 96 or 224 columns; widths with
+// only the 32-column tile are skipped), never above kp.
 int launch_width(const ladmm_batch *b, int n) {
-  const int unit = bf16_block(b->c->precision) ? 112 : 32;
-  return std::min(b->kp, std::max(unit, round_up(n, unit)));
+  const bool bf = bf16_block(b->c->precision);
+  for (int w = round_up(std::max(n, 1), 32); w < b->kp; w += 32)
+    if (!bf || w % 64 == 0 || w % 96 == 0 || w % 224 == 0) return w;
+  return b->kp;
 }
 
 // Between check chunks of a run: move the running plans to the lowest columns

@@ -127,7 +127,7 @@ ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
 
 
 # compaction runs: enough plans for the launched width to shrink (FP32 in
-# 32-column steps, BF16 in 112-column steps)
+# 32-column steps, BF16 in widths that admit a 64-, 96- or 224-column tile)
 COMPACT_CASES = [("f32", 70), ("bf16", 120)]
 
 
@@ -220,7 +220,7 @@ def _prepare(root):
     for precision, k in COMPACT_CASES:
         case, w = _iter_spec(k)
         d = os.path.join(root, f"compact-{precision}")
-        write_inputs(d, case, w, precision, 1, tiles=(0, 0), compact_iters=8)
+        write_inputs(d, case, w, precision, 1, tiles=(0, 0), compact_iters=12)
         runs[f"compact-{precision}"] = d
     return runs
 
