@@ -172,6 +172,30 @@ def parse():
     return ap.parse_args()
 
 
+_T0 = time.perf_counter()
+PHASES = {}
+
+
+def log(msg):
+    """Progress on stderr (a long run keeps printing while it works)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
+class phase:
+    """Times one phase of the benchmark into PHASES and logs its start and end."""
+
+    def __init__(self, name):
+        self.name = name
+
+    def __enter__(self):
+        log(self.name + " ...")
+        self.t = time.perf_counter()
+
+    def __exit__(self, *exc):
+        PHASES[self.name] = round(time.perf_counter() - self.t, 2)
+        log(f"{self.name}: {PHASES[self.name]} s")
+
+
 def host_cpu():
     """Host cores and model of the machine running the oracle (nproc, lscpu)."""
     info = {"nproc": os.cpu_count()}
@@ -204,14 +228,18 @@ def cpu_baseline(case, w, rho0, budget_s, gpu_plan_iterations=None):
     slp = olp.precondition(lp, olp.bot_scale(case))
     del lp
     rho = olp.rho_rule(w[:, 3], rho0, cases.W0_BOT)
+    log("oracle: LP assembled and preconditioned")
     fac, _ = oadmm.schur_factor(slp)
+    log("oracle: Schur complement factored")
     st = oadmm.admm_iterate(slp, rho, 1, factor=fac)     # warm-up
+    log("oracle: warm-up iteration done")
     setup_s = time.perf_counter() - t_setup
     iters = 0
     t0 = time.perf_counter()
     while iters == 0 or time.perf_counter() - t0 < budget_s:
         st = oadmm.admm_iterate(slp, rho, 1, st, fac)
         iters += 1
+        log(f"oracle: {iters} timed iterations")
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     value = iters * w.shape[0] / dt
@@ -393,7 +421,10 @@ def product_bytes(kernel, precision, N, n_t, k, kp):
 def sweep(dc, w, opts, label):
     from paper_2509_08602_amd import ladmm
     t1 = time.perf_counter()
-    out = ladmm.solve_batch(dc, w, opts=opts)
+    b = ladmm.Batch(dc, w, opts=opts)
+    b.run(progress=lambda running: log(f"{label}: {running} plans still running"))
+    out = b.results()
+    b.close()
     sec = time.perf_counter() - t1
     conv = out["plan_status"] == ladmm.PLAN_CONVERGED
     return dict(label=label, plans=int(w.shape[0]), seconds=round(sec, 4),
@@ -419,14 +450,15 @@ def main():
 
     cfg = args.config
     precision = args.precision or DEFAULT_PRECISION[cfg]
-    t_case = time.perf_counter()
-    case = cases.make_case(cfg)
-    case_s = time.perf_counter() - t_case
+    with phase("case build"):
+        case = cases.make_case(cfg)
+    case_s = PHASES["case build"]
     w = cases.config_weights(cfg)
     k = w.shape[0]
     rho0 = RHO0
     ctx = ladmm.Context(0)
-    dc = ladmm.Case.from_case(ctx, case, precision)
+    with phase("case setup on the device"):
+        dc = ladmm.Case.from_case(ctx, case, precision)
     setup_ms = dc.setup_ms
     fixed = ladmm.Options(max_iter=ITERS_PER_STEP, check_every=ITERS_PER_STEP, tol_gap=0.0,
                           rho0=rho0, w0_bot=cases.W0_BOT)
@@ -440,18 +472,22 @@ def main():
 
     # timed region: each step replays the captured graph of one check chunk
     b.set_graphs(args.launch == "graph")
-    for _ in range(args.warmup):
-        b.iterate(ITERS_PER_STEP)
-    wall = timed(args.steps)
+    with phase("warm-up steps"):
+        for _ in range(args.warmup):
+            b.iterate(ITERS_PER_STEP)
+    with phase("timed steps"):
+        wall = timed(args.steps)
     # kernel durations: HIP events around every launch on the batch's stream
     # (this launches kernel by kernel), the same number of steps right after
     b.set_profiling(True)
-    wall_prof = timed(args.steps)
+    with phase("steps with kernel events"):
+        wall_prof = timed(args.steps)
     ktimes = b.kernel_times()
     b.set_profiling(False)
     # one-by-one launches without events, for the launch-mode comparison
     b.set_graphs(False)
-    wall_eager = timed(args.steps)
+    with phase("steps launched one by one"):
+        wall_eager = timed(args.steps)
     tiles = b.tiles()
     res = b.results(with_t=False)
     kp = -(-k // 32) * 32
@@ -511,16 +547,20 @@ def main():
         opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=args.tol_cert, tol_pri=1e-4,
                              tol_dual=1e-4, tol_cert=args.tol_cert, rho0=rho0,
                              w0_bot=cases.W0_BOT, alpha=args.alpha)
-        sweeps = {"pass1": sweep(dc, w, opts, f"{precision}, pass 1")}
+        with phase("sweep, pass 1"):
+            sweeps = {"pass1": sweep(dc, w, opts, f"{precision}, pass 1")}
         gpu_plan_iterations = sweeps["pass1"]["plan_iterations"]
         sweeps["pass1"]["paper_budget_2x3000_seconds"] = round(2 * 3000 * k / value, 2)
-        two = two_pass_sweep(ctx, case, w, precision, opts)
+        with phase("sweep, both passes"):
+            two = two_pass_sweep(ctx, case, w, precision, opts)
         if two:
             sweeps["two_pass"] = two
         if not args.no_f64_sweep and precision != "f64":
             dc.close()
-            d64 = ladmm.Case.from_case(ctx, case, "f64")
-            sweeps["f64_pass1"] = sweep(d64, w, opts, "plain FP64 GPU ADMM, pass 1")
+            with phase("FP64 case setup"):
+                d64 = ladmm.Case.from_case(ctx, case, "f64")
+            with phase("sweep, plain FP64 GPU ADMM"):
+                sweeps["f64_pass1"] = sweep(d64, w, opts, "plain FP64 GPU ADMM, pass 1")
             sweeps["f64_pass1"]["speedup_of_" + precision] = round(
                 sweeps["f64_pass1"]["seconds"] / sweeps["pass1"]["seconds"], 2)
             d64.close()
@@ -530,7 +570,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, w, rho0, args.cpu_seconds, gpu_plan_iterations)
+        with phase("CPU oracle baseline"):
+            cpu = cpu_baseline(case, w, rho0, args.cpu_seconds, gpu_plan_iterations)
 
     line = {
         "metric": "plan-iterations/s",
@@ -559,6 +600,7 @@ def main():
         "sweeps": sweeps,
         "last_check": {"max_rel_gap": float(np.max(res["rel_gap"])),
                        "max_r_pri": float(np.max(res["r_pri"]))},
+        "phase_seconds": PHASES,
     }
     print(json.dumps(line))
 

@@ -229,6 +229,11 @@ int ladmm_batch_destroy(ladmm_batch *b);
 int ladmm_batch_iterate(ladmm_batch *b, int32_t iters);
 /* Iterate with checks until every plan has stopped or max_iter is reached. */
 int ladmm_batch_run(ladmm_batch *b);
+/* The same, returning after at most max_checks check chunks (>= 1) with
+ * *running (optional) = plans still running; call again to continue.  Plans
+ * that stop keep their results; a run continued in several calls gives the
+ * same results as one ladmm_batch_run. */
+int ladmm_batch_run_checks(ladmm_batch *b, int32_t max_checks, int32_t *running);
 /* Evaluate the per-plan statistics at the current iterate and fill `out`. */
 int ladmm_batch_results(ladmm_batch *b, ladmm_result *out);
 /* Iterates in the oracle's variables (scaled LP of Sec. 3.C), host FP64,

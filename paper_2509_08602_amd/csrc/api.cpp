@@ -1385,16 +1385,25 @@ int run_chunk(ladmm_batch *b, int n, bool decide) {
   return LADMM_OK;
 }
 
-int run_impl(ladmm_batch *b) {
+// Run check chunks until every plan has stopped or max_iter is reached, or
+// until max_checks chunks have run (max_checks <= 0: no limit).  The running
+// plans are compacted between chunks and return to their own columns before
+// this returns.  *running (optional): plans still running.
+int run_impl(ladmm_batch *b, int max_checks = 0, int32_t *running = nullptr) {
   HIPC(hipSetDevice(b->c->ctx->device));
   const int every = b->opts.check_every;
-  while (b->iters_run < b->opts.max_iter) {
-    bool any = false;
-    for (int j = 0; j < b->k; ++j) any |= b->h_active[j] != 0;
-    if (!any) break;
+  int checks = 0;
+  auto count_running = [&]() {
+    int n = 0;
+    for (int j = 0; j < b->k; ++j) n += b->h_active[j] != 0;
+    return n;
+  };
+  while (b->iters_run < b->opts.max_iter && count_running() > 0 &&
+         (max_checks <= 0 || checks < max_checks)) {
     const int n = std::min(every, b->opts.max_iter - b->iters_run);
     int rc = run_chunk(b, n, true);
     if (rc) return rc;
+    ++checks;
     if (b->compact) {
       rc = compact(b);
       if (rc) return rc;
@@ -1402,8 +1411,15 @@ int run_impl(ladmm_batch *b) {
   }
   int rc = uncompact(b);
   if (rc) return rc;
-  for (int j = 0; j < b->k; ++j)
-    if (b->status[j] == LADMM_PLAN_RUNNING) b->status[j] = LADMM_PLAN_MAX_ITER;
+  const bool done = b->iters_run >= b->opts.max_iter || count_running() == 0;
+  if (done) {
+    for (int j = 0; j < b->k; ++j)
+      if (b->status[j] == LADMM_PLAN_RUNNING) {
+        b->status[j] = LADMM_PLAN_MAX_ITER;
+        b->h_active[j] = 0;
+      }
+  }
+  if (running) *running = done ? 0 : count_running();
   return LADMM_OK;
 }
 
@@ -1559,6 +1575,12 @@ int ladmm_batch_iterate(ladmm_batch *b, int32_t iters) {
 int ladmm_batch_run(ladmm_batch *b) {
   if (!b) return fail(LADMM_E_STATE, "null batch");
   return run_impl(b);
+}
+
+int ladmm_batch_run_checks(ladmm_batch *b, int32_t max_checks, int32_t *running) {
+  if (!b) return fail(LADMM_E_STATE, "null batch");
+  if (max_checks < 1) return fail(LADMM_E_INVALID, "max_checks must be >= 1");
+  return run_impl(b, max_checks, running);
 }
 
 int ladmm_batch_results(ladmm_batch *b, ladmm_result *out) {

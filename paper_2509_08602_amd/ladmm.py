@@ -129,6 +129,7 @@ _SIGS = {
     "ladmm_batch_timing": (C.c_int, [C.c_void_p, _DP, C.POINTER(C.c_int64)]),
     "ladmm_batch_step_sizes": (C.c_int, [C.c_void_p, _DP]),
     "ladmm_batch_set_compaction": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ladmm_batch_run_checks": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "ladmm_batch_set_graphs": (C.c_int, [C.c_void_p, C.c_int32]),
     "ladmm_batch_metrics": (C.c_int, [C.c_void_p, C.c_int64, _DP, _IP, C.c_int32, _DP, C.c_double,
                                       _DP]),
@@ -354,8 +355,17 @@ class Batch:
     def iterate(self, n: int):
         _check(library().ladmm_batch_iterate(self._h, int(n)))
 
-    def run(self):
-        _check(library().ladmm_batch_run(self._h))
+    def run(self, progress=None, checks_per_call=20):
+        """Iterate until every plan has stopped.  With progress(running,
+        iterations_run) the run returns to Python every checks_per_call checks
+        to report the plans still running."""
+        if progress is None:
+            _check(library().ladmm_batch_run(self._h))
+            return
+        running = C.c_int32(1)
+        while running.value > 0:
+            _check(library().ladmm_batch_run_checks(self._h, int(checks_per_call), C.byref(running)))
+            progress(int(running.value))
 
     def results(self, with_t=True):
         k, c = self.k, self.case

@@ -484,21 +484,31 @@ def test_refinement_refresh_step_matches_oracle_c1(ctx, c1):
 def test_compaction_gives_identical_results(ctx, c0, precision):
     """441 plans on the small case, stopping at different checks: a run that
     compacts the running plans into the lowest columns (launching fewer
-    columns) gives every plan the same bits as a run that does not."""
+    columns) gives every plan the same bits as a run that does not, and as a
+    run continued over several calls of ladmm_batch_run_checks."""
     say("compaction on/off c0", precision)
     w = cases.config_weights(2)
     dc = ladmm.Case.from_case(ctx, c0, precision)
     opts = ladmm.Options(max_iter=3000, check_every=50, tol_gap=1e-3, tol_pri=1e-3, tol_dual=1e-3,
                          rho0=1e4, w0_bot=cases.W0_BOT, adapt_rho=True)
     out = {}
-    for on in (True, False):
+    for mode in ("on", "off", "chunked"):
         b = ladmm.Batch(dc, w, opts=opts)
-        b.set_compaction(on)
-        b.run()
-        out[on] = (b.results(), b.export(), b.step_sizes(), b.timing())
+        b.set_compaction(mode != "off")
+        if mode == "chunked":
+            # a run continued over several calls of a few checks each
+            b.run(progress=lambda running: None, checks_per_call=3)
+        else:
+            b.run()
+        out[mode] = (b.results(), b.export(), b.step_sizes(), b.timing())
         b.close()
-    ra, ea, rhoa, ta = out[True]
-    rb, eb, rhob, tb = out[False]
+    ra, ea, rhoa, ta = out["on"]
+    rb, eb, rhob, tb = out["off"]
+    rc, ec, rhoc, _ = out["chunked"]
+    for key in ra:
+        assert np.array_equal(ra[key], rc[key], equal_nan=True), key
+    for x, y in zip(ea, ec):
+        assert np.array_equal(x, y)
     say("  iterations: distinct", len(set(ra["iters"].tolist())), "max", ra["iters"].max(),
         "device ms with / without compaction", round(ta[0], 1), round(tb[0], 1))
     assert len(set(ra["iters"].tolist())) > 3
