@@ -353,6 +353,21 @@ int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint6
                            const int32_t *n_ld, uint64_t seed, int64_t *P, int64_t *nP,
                            uint64_t *masks);
 
+/* The same selection, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid hipMalloc):
+ * it calls no hipMalloc, hipFree or other allocating routine and creates no
+ * stream.  Its work arrays, the staged inputs and the outputs live in one
+ * library-owned device array of 32 MiB per device (held until the process
+ * ends), launched on the null stream.  Arguments, layouts and results are
+ * those of ladmm_select_ld_points, bit for bit.  LADMM_E_INVALID when the call
+ * needs more than the 32 MiB: 8 (7 + 64 + 3 k) ceil(n_vox/64) + 8 n_vox + 16 k
+ * bytes plus alignment, e.g. k = 441 plans of up to 60,000 candidate voxels.
+ * Calls on one device share the array and are serialized by the library
+ * (the array keeps the last call's contents; every call writes what it reads). */
+int ladmm_select_ld_points_static(ladmm_ctx *ctx, int32_t k, int64_t n_vox,
+                                  const uint64_t *vol_bits, const int32_t *n_ld, uint64_t seed,
+                                  int64_t *P, int64_t *nP, uint64_t *masks);
+
 /* Second pass of the two-pass optimisation (Sec. 2.C): how the low-dose points
  * of the second-pass problem are chosen from the first-pass dose.
  *   n_vox, phi_vox: candidate voxels of the patient volume and their dose rates

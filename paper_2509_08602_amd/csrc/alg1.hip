@@ -17,9 +17,44 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "kernels.h"
 
 namespace ladmm {
+
+// Scratch of the allocation-free Algorithm 1 entry point: one file-scope
+// device array per device, never freed.  In host code its name is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per device
+// with that device current, and only that address is handed to kernels and
+// copies.
+namespace {
+constexpr size_t kAlg1ScratchBytes = (size_t)32 << 20;   // 32 MiB
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kAlg1ScratchBytes];
+std::mutex g_scratch_mu[kMaxDevices];
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t alg1_scratch_bytes() { return kAlg1ScratchBytes; }
+
+std::mutex *alg1_scratch_lock(int device) {
+  return device >= 0 && device < kMaxDevices ? &g_scratch_mu[device] : nullptr;
+}
+
+// The device address of `scratch` on `device` (which must be current); the
+// caller holds alg1_scratch_lock(device).
+hipError_t alg1_scratch(int device, unsigned char **ptr) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (unsigned char *)p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 namespace {
 

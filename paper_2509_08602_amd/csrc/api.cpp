@@ -1951,6 +1951,72 @@ int ladmm_select_ld_points(ladmm_ctx *ctx, int32_t k, int64_t n_vox, const uint6
   return LADMM_OK;
 }
 
+int ladmm_select_ld_points_static(ladmm_ctx *ctx, int32_t k, int64_t n_vox,
+                                  const uint64_t *vol_bits, const int32_t *n_ld, uint64_t seed,
+                                  int64_t *P, int64_t *nP, uint64_t *masks) {
+  if (!ctx) return fail(LADMM_E_STATE, "null context");
+  if (k < 0 || n_vox < 1 || !nP || (k > 0 && (!vol_bits || !n_ld || !P || !masks)))
+    return fail(LADMM_E_INVALID, "select_ld_points_static: bad arguments");
+  if (n_vox > (int64_t)1 << 31) return fail(LADMM_E_INVALID, "select_ld_points_static: too many voxels");
+  const int W = (int)((n_vox + 63) / 64);
+  if (k == 0) {
+    *nP = 0;
+    return LADMM_OK;
+  }
+  if (n_vox % 64)
+    for (int j = 0; j < k; ++j)
+      if (vol_bits[(size_t)j * W + W - 1] >> (n_vox % 64))
+        return fail(LADMM_E_INVALID, "select_ld_points_static: bits set past n_vox");
+  // layout in the scratch array: the same buffers as ladmm_select_ld_points
+  // allocates, each 256-byte aligned
+  const size_t wb = (size_t)W * sizeof(uint64_t);
+  const size_t sizes[] = {wb, wb, wb, wb, wb, wb, wb, wb * 64, wb * (size_t)k,
+                          (size_t)k * sizeof(int64_t), (size_t)k * sizeof(int32_t),
+                          (size_t)W * sizeof(int64_t), wb * (size_t)k, wb * (size_t)k,
+                          (size_t)k * sizeof(int32_t), (size_t)n_vox * sizeof(int64_t),
+                          sizeof(int64_t)};
+  constexpr int kBufs = sizeof(sizes) / sizeof(sizes[0]);
+  size_t off[kBufs], need = 0;
+  for (int i = 0; i < kBufs; ++i) {
+    off[i] = need;
+    need += (sizes[i] + 255) / 256 * 256;
+  }
+  if (need > alg1_scratch_bytes())
+    return fail(LADMM_E_INVALID, "select_ld_points_static: needs " + std::to_string(need) +
+                                     " bytes of scratch, more than its " +
+                                     std::to_string(alg1_scratch_bytes()) +
+                                     " (use ladmm_select_ld_points)");
+  std::mutex *mu = alg1_scratch_lock(ctx->device);
+  if (!mu) return fail(LADMM_E_INVALID, "select_ld_points_static: device index out of range");
+  std::lock_guard<std::mutex> lk(*mu);
+  HIPC(hipSetDevice(ctx->device));
+  unsigned char *base = nullptr;
+  HIPC(alg1_scratch(ctx->device, &base));
+  auto at = [&](int i) { return (void *)(base + off[i]); };
+  Alg1Work wk{};
+  wk.Vu = (uint64_t *)at(0); wk.pu = (uint64_t *)at(1); wk.pt = (uint64_t *)at(2);
+  wk.nw = (uint64_t *)at(3); wk.po = (uint64_t *)at(4); wk.tmp = (uint64_t *)at(5);
+  wk.uni = (uint64_t *)at(6); wk.keys = (uint64_t *)at(7); wk.pj = (uint64_t *)at(8);
+  wk.vsize = (int64_t *)at(9); wk.order = (int32_t *)at(10); wk.offs = (int64_t *)at(11);
+  uint64_t *dvols = (uint64_t *)at(12), *dmasks = (uint64_t *)at(13);
+  int32_t *dn = (int32_t *)at(14);
+  int64_t *dP = (int64_t *)at(15), *dnP = (int64_t *)at(16);
+  // the null stream: nothing is created; every array the kernels read is
+  // written by this call first (inputs copied, work arrays set by the kernels)
+  hipStream_t s = nullptr;
+  HIPC(hipMemcpyAsync(dvols, vol_bits, wb * k, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(dn, n_ld, (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPC(alg1_select(s, k, n_vox, dvols, dn, seed, wk, dP, dnP, dmasks, W));
+  int64_t hn = 0;
+  HIPC(hipMemcpyAsync(&hn, dnP, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  if (hn > 0) HIPC(hipMemcpyAsync(P, dP, (size_t)hn * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(masks, dmasks, wb * k, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  *nP = hn;
+  return LADMM_OK;
+}
+
 int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const ladmm_weights *w,
                  const ladmm_opts *opts, int32_t n_sets, const ladmm_pass2_desc *sets,
                  int32_t n_passes, ladmm_result *pass_out, int64_t *P_out, int64_t *n_points,

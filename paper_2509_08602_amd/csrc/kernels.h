@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace ladmm {
 
 // Tile sizes shared by the launchers and the host-side padding rules.
@@ -167,6 +169,12 @@ struct Alg1Work {
 // vols: k x W words (device); P: n_vox capacity; masks: k rows of ldm >= W words.
 hipError_t alg1_select(hipStream_t s, int k, int64_t n_vox, const uint64_t *vols, const int32_t *n_ld,
                        uint64_t seed, Alg1Work &wk, int64_t *P, int64_t *nP, uint64_t *masks, int ldm);
+// Scratch of the allocation-free Algorithm 1: a file-scope device array of
+// alg1_scratch_bytes() per device; alg1_scratch gives its device address on
+// `device` (current), to be used under alg1_scratch_lock(device).
+size_t alg1_scratch_bytes();
+hipError_t alg1_scratch(int device, unsigned char **ptr);
+std::mutex *alg1_scratch_lock(int device);
 // bits[j][v / 64] bit v % 64 = (lo <= d[v][j] < hi), d: n_vox rows of ldd.
 hipError_t band_bits(hipStream_t s, const double *d, int ldd, int n_vox, int k, double lo, double hi,
                      uint64_t *bits);

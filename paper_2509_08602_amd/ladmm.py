@@ -144,6 +144,10 @@ _SIGS = {
     "ladmm_select_ld_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_uint64),
                                          _IP, C.c_uint64, C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "ladmm_select_ld_points_static": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64,
+                                                C.POINTER(C.c_uint64), _IP, C.c_uint64,
+                                                C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                                C.POINTER(C.c_uint64)]),
     "ladmm_two_pass": (C.c_int, [C.c_void_p, C.POINTER(_CaseDesc), C.c_int32, C.POINTER(_Weights),
                                  C.POINTER(_Opts), C.POINTER(_Pass2), C.c_void_p,
                                  C.POINTER(_Result), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -594,9 +598,10 @@ def unpack(words, n):
     return bits.reshape(words.shape[0], -1)[:, :n].astype(bool)
 
 
-def select_ld_points(ctx: Context, volumes, n_ld, seed: int):
-    """Algorithm 1 on the device.  volumes: k x n_vox bool (or k x W uint64 with
-    n_vox given as volumes.n_vox).  Returns (P, masks) with masks k x |P| bool."""
+def select_ld_points(ctx: Context, volumes, n_ld, seed: int, static: bool = False):
+    """Algorithm 1 on the device.  volumes: k x n_vox bool.  Returns (P, mask
+    words, masks) with masks k x |P| bool.  static: the allocation-free entry
+    point (ladmm_select_ld_points_static)."""
     vols = np.asarray(volumes)
     k, n_vox = vols.shape
     bits = _mask_words(vols, n_vox) if k else np.zeros((0, (n_vox + 63) // 64), np.uint64)
@@ -605,7 +610,8 @@ def select_ld_points(ctx: Context, volumes, n_ld, seed: int):
     P = np.zeros(n_vox, np.int64)
     nP = C.c_int64()
     masks = np.zeros((max(k, 1), W), np.uint64)
-    _check(library().ladmm_select_ld_points(
+    fn = library().ladmm_select_ld_points_static if static else library().ladmm_select_ld_points
+    _check(fn(
         ctx._h, k, n_vox, bits.ctypes.data_as(C.POINTER(C.c_uint64)), n.ctypes.data_as(_IP),
         C.c_uint64(int(seed) & ((1 << 64) - 1)), P.ctypes.data_as(C.POINTER(C.c_int64)),
         C.byref(nP), masks.ctypes.data_as(C.POINTER(C.c_uint64))))

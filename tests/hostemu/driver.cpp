@@ -1,3 +1,4 @@
+#include <algorithm>
 // Drives libladmm's C ABI, built for the host emulation, on inputs written by
 // the Python test (tests/test_hostemu.py), and writes what it computed.
 //   driver <dir>   reads  <dir>/meta.txt, dose.f64, group.i32, groups.txt,
@@ -148,6 +149,17 @@ int main(int argc, char **argv) {
     CHECK(ladmm_select_ld_points(ctx, n_vols, n_vox, vols.data(), nld.data(), seed, P.data(), &nP, masks.data()));
     save(dir + "/P.i64", P.data(), (size_t)nP);
     save(dir + "/masks.u64", masks.data(), masks.size());
+    // the allocation-free variant (static scratch), twice: the second call on
+    // the first plans only (a smaller input into the used scratch)
+    for (int rep = 0; rep < 2; ++rep) {
+      const int kk = rep == 0 ? n_vols : std::max(1, n_vols / 2);
+      std::fill(P.begin(), P.end(), -1);
+      std::fill(masks.begin(), masks.end(), 0);
+      CHECK(ladmm_select_ld_points_static(ctx, kk, n_vox, vols.data(), nld.data(), seed, P.data(), &nP,
+                                          masks.data()));
+      save(dir + "/P_static" + std::to_string(rep) + ".i64", P.data(), (size_t)nP);
+      save(dir + "/masks_static" + std::to_string(rep) + ".u64", masks.data(), (size_t)kk * Wv);
+    }
   }
   if (band_vox > 0 && run_two_pass) {
     // both passes, a few fixed iterations each

@@ -51,6 +51,7 @@ void launch(dim3 grid, dim3 block, std::function<void()> body);
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
 
 inline void __syncthreads() { hostemu::barrier(); }
 
@@ -158,7 +159,8 @@ inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v)
 typedef int hipError_t;
 typedef void *hipStream_t;
 typedef struct hostemu_event *hipEvent_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorNoDevice = 3 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorNoDevice = 3,
+       hipErrorInvalidDevice = 4 };
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost,
                      hipMemcpyDeviceToDevice, hipMemcpyDefault };
 #define hipHostMallocDefault 0
@@ -186,6 +188,12 @@ hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipEventRecord(hipEvent_t, hipStream_t);
 hipError_t hipEventSynchronize(hipEvent_t);
 hipError_t hipEventElapsedTime(float *, hipEvent_t, hipEvent_t);
+// A file-scope __device__ array is a host array here; its address is its symbol's.
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+  *p = const_cast<void *>(symbol);
+  return hipSuccess;
+}
 
 // Stream capture: kernel launches of the capturing thread are recorded into the
 // graph and run, in order, at each hipGraphLaunch.  Any other stream operation

@@ -321,6 +321,13 @@ def test_emulated_ld_mask_oar_band_and_alg1(emu):
     W = (700 + 63) // 64
     masks = rd(d, "masks.u64", (6, W), np.uint64)
     assert np.array_equal(cases.unpack_bits(masks, len(Pref)), oalg1.masks_over(Pref, pref))
+    # the allocation-free entry point: the same bits, then a smaller second call
+    for rep, kk in ((0, 6), (1, 3)):
+        Pk, pk = (Pref, pref) if kk == 6 else oalg1.select_ld_points(vols[:kk], n_ld[:kk], 77)
+        Ps = np.fromfile(os.path.join(d, f"P_static{rep}.i64"), np.int64)
+        assert Ps.tolist() == Pk
+        ms = rd(d, f"masks_static{rep}.u64", (kk, W), np.uint64)
+        assert np.array_equal(cases.unpack_bits(ms, len(Pk)), oalg1.masks_over(Pk, pk))
     # low-dose band of the current shot times
     t = rd(d, "t.f64", (4, lp.n_t))
     band = cases.unpack_bits(rd(d, "band.u64", (4, (333 + 63) // 64), np.uint64), 333)
