@@ -488,12 +488,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
 // same order as k_gemm_bf, so both kernels give the same bits.  LDS traffic per
 // k-step and wave: 2 TN fragment reads for 3 TM TN MFMAs, against 2 (TM + TN)
 // with A staged too.
-template <int TM, int TN, int WM, int PD, int TERMS, int MODE, int DL>
-__global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K, int kchunk,
-                                                      int mtiles, int ntiles,
-                                                      float *__restrict__ P, int ldp,
-                                                      size_t pstride, EpiArgs<float> ea) {
-  constexpr int BM = TM * 16 * WM, BN = TN * 16, NT = 64 * WM;
+//
+// WN > 1: the waves form a WM x WN grid and also split the columns; a
+// workgroup then spans up to all plan columns of a batch (the dose block is read
+// once per product), the waves of a row share its A fragments (the second load
+// of a fragment hits the cache) and each wave reads only its own TN column
+// tiles of B from LDS.
+template <int TM, int TN, int WM, int WN, int PD, int TERMS, int MODE, int DL>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bfd(BfPair A, BfPair B, int K, int kchunk,
+                                                           int mtiles, int ntiles,
+                                                           float *__restrict__ P, int ldp,
+                                                           size_t pstride, EpiArgs<float> ea) {
+  constexpr int BM = TM * 16 * WM, BN = TN * 16 * WN, NT = 64 * WM * WN;
   constexpr int KV = kBfBK / 8;
   constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
   static_assert(TERMS == 1 || TERMS == 3, "one or three products per k step");
@@ -511,12 +517,14 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
   auto sBl = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem + kTileB);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
   const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
   const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
   const int m0 = mt * BM, n0 = nt * BN;
   const int kbeg = MODE == 0 ? zc * kchunk : 0;
   const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
   const int g8 = 8 * (lane >> 4), r16 = lane & 15;
+  const int bcol = wn * TN * 16;   // this wave's first column in the workgroup's B tile
 
   f4v acc[TM][TN];
 #pragma unroll
@@ -527,7 +535,7 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
   // register ring: slot 0 holds the stage being multiplied, slot p the stage p
   // ahead.  A fragment of 16-row tile t at k step k0 / 32: 1 KiB at
   // frag_off(16 t, k0, K); this lane's piece is 8 lane elements further.
-  const size_t arow = frag_off(m0 + wave * TM * 16, 0, A.ld) + (size_t)lane * 8;
+  const size_t arow = frag_off(m0 + wm * TM * 16, 0, A.ld) + (size_t)lane * 8;
   const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
   uint4 ah[PD + 1][TM], al[PD + 1][TA], rbh[PD + 1][BVT], rbl[PD + 1][BVL];
   auto load = [&](int k0, int slot) {
@@ -573,8 +581,8 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
       bf8v bh[TN], bl[ALO ? TN : 1];
 #pragma unroll
       for (int tn = 0; tn < TN; ++tn) {
-        bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][tn * 16 + r16][g8]);
-        if (ALO) bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][tn * 16 + r16][g8]);
+        bh[tn] = *reinterpret_cast<const bf8v *>(&sBh[buf][bcol + tn * 16 + r16][g8]);
+        if (ALO) bl[tn] = *reinterpret_cast<const bf8v *>(&sBl[buf][bcol + tn * 16 + r16][g8]);
       }
       // term-major: TM TN independent products between two on one accumulator
 #pragma unroll
@@ -611,7 +619,7 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
       }
     }
   }
-  bf_epilogue<BM, BN, WM, 1, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+  bf_epilogue<BM, BN, WM, WN, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
 }
 
 // Tile configurations of the split-K product (which = 0) and the point-row
@@ -619,16 +627,17 @@ __global__ __launch_bounds__(64 * WM) void k_gemm_bfd(BfPair A, BfPair B, int K,
 // through LDS, k_gemm_bf) or direct (A from global memory, k_gemm_bfd).
 // Configuration 0 is valid for every padded shape (M % 64, N % 32).
 // Configurations 6 and 7 are for single-operand products only (terms = 1):
-// a workgroup covers all 448 plan columns of a 441-plan batch (or 224), so the
-// dose block is read once per product; 8 (point-row) or 4 (split-K) waves
-// split rows and columns and share both operand tiles through LDS.
+// direct-A kernels whose waves form a 2 x 2 (4 x 2) grid, each wave 32 rows x
+// 224 columns (split-K 7: 112), so a workgroup covers all 448 plan columns of
+// a 441-plan batch (split-K 7: 224) and the dose block is read once per
+// product.
 constexpr int kBfCfgCount = 8;
 struct BfCfg { int bm, bn; bool single_only; };
 static const BfCfg kBfCfgs[2][kBfCfgCount] = {
     {{64, 32, false}, {64, 64, false}, {192, 112, false}, {160, 112, false}, {64, 96, false},
      {192, 64, false}, {64, 448, true}, {64, 224, true}},
     {{64, 32, false}, {256, 64, false}, {128, 112, false}, {128, 112, false}, {128, 96, false},
-     {128, 64, false}, {128, 448, true}, {128, 224, true}}};
+     {128, 64, false}, {128, 448, true}, {64, 448, true}}};
 
 bool gemm_bf_cfg_ok(int which, int cfg, int M, int N, int terms) {
   if (cfg < 0 || cfg >= kBfCfgCount) return false;
@@ -648,8 +657,11 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
   hipLaunchKernelGGL((k_gemm_bf<BMv, BNv, WMv, WNv, TERMS, MODE, NB, DL>), grid, dim3(64 * WMv * WNv), 0, \
                      s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
 #define BF_DI(TMv, TNv, WMv)                                                                       \
-  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
+  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
                      K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
+#define BF_DW(TMv, TNv, WMv, WNv)                                                                  \
+  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, WNv, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv * WNv), \
+                     0, s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
   if constexpr (MODE == 0) {
     switch (cfg) {
       case 0: BF_ST(64, 32, 2, 1, 2); break;
@@ -659,10 +671,10 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(1, 6, 4); break;
       case 5: BF_DI(3, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_ST(64, 448, 1, 4, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 14, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_ST(64, 224, 1, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 7, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
@@ -675,16 +687,17 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(2, 6, 4); break;
       case 5: BF_DI(2, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_ST(128, 448, 2, 4, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 14, 4, 2); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_ST(128, 224, 2, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 14, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
   }
 #undef BF_ST
 #undef BF_DI
+#undef BF_DW
   return hipGetLastError();
 }
 

@@ -122,8 +122,10 @@ ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
               # iterates carry BF16 rounding (2^-9 relative per operand) until
               # the refresh that ends the chunk
               ("bf16", 3e-2, (-1, -1), 12, 5),
-              # the single-operand tiles that span 224 plan columns per workgroup
-              ("bf16", 3e-2, (7, 7), 0, 224)]
+              # the single-operand tiles whose waves split rows and columns, a
+              # workgroup spanning 224 or 448 plan columns
+              ("bf16", 3e-2, (6, 6), 0, 448),
+              ("bf16", 3e-2, (7, 7), 0, 448)]
 
 
 # compaction runs: enough plans for the launched width to shrink (FP32 in
