@@ -622,15 +622,116 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bfd(BfPair A, BfPair B, i
   bf_epilogue<BM, BN, WM, WN, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
 }
 
+// Single-operand products (terms = 1, LADMM_BF16's hot iterations).  With one
+// MFMA per accumulator and k step, a step's MFMA work (TM TN per wave) is a
+// third of the pair products', too short to hide a dose-block fetch from HBM
+// behind one stage of prefetch.  Here the A fragments (the dose block, read
+// once per product) run PDA k steps ahead in a register ring, and B (the small
+// plan-side operand, served by L2) one step ahead through two LDS stages; each
+// B fragment is read from LDS right before the TM MFMAs that use it.  The waves
+// form a WM x WN grid (a workgroup spans up to all plan columns).  Every
+// accumulator takes one MFMA per k step in k order, as in the other kernels,
+// so the results are the same bits.
+template <int TM, int TN, int WM, int WN, int PDA, int MODE, int DL>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_b1(BfPair A, BfPair B, int K, int kchunk,
+                                                          int mtiles, int ntiles,
+                                                          float *__restrict__ P, int ldp,
+                                                          size_t pstride, EpiArgs<float> ea) {
+  constexpr int BM = TM * 16 * WM, BN = TN * 16 * WN, NT = 64 * WM * WN;
+  constexpr int KV = kBfBK / 8;
+  constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
+  static_assert(PDA >= 1, "prefetch distance");
+  static_assert(MODE == 0 || (TM * 16) % 32 == 0, "statistics partials are per 32-row block");
+  constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
+  constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE, DL>();
+  constexpr size_t kBytes = kTileB > kBytesR ? kTileB : kBytesR;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  auto sB = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int tile = xcd_tile_bf(blockIdx.x, gridDim.x);
+  const int nt = tile % ntiles, mt = (tile / ntiles) % mtiles, zc = tile / (mtiles * ntiles);
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int kbeg = MODE == 0 ? zc * kchunk : 0;
+  const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
+  const int g8 = 8 * (lane >> 4), r16 = lane & 15;
+  const int bcol = wn * TN * 16;
+
+  f4v acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
+
+  const size_t arow = frag_off(m0 + wm * TM * 16, 0, A.ld) + (size_t)lane * 8;
+  const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
+  uint4 ah[PDA + 1][TM], rb[BVT];
+  auto load_a = [&](int k0, int slot) {
+    const bool in = k0 + g8 < kend;
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) {
+      const size_t off = arow + tm * astep + (size_t)(k0 >> 5) * 512;
+      ah[slot][tm] = in ? *reinterpret_cast<const uint4 *>(A.hi + off) : uint4{0, 0, 0, 0};
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) {
+        const int row = e / KV, k = k0 + (e % KV) * 8;
+        const size_t off = (size_t)(n0 + row) * B.ld + k;
+        rb[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
+      }
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) {
+      const int e = tid + i * NT;
+      if (e < BV) *reinterpret_cast<uint4 *>(&sB[buf][e / KV][(e % KV) * 8]) = rb[i];
+    }
+  };
+
+  if (kbeg < kend) {
+#pragma unroll
+    for (int p = 0; p < PDA; ++p)
+      if (kbeg + p * kBfBK < kend) load_a(kbeg + p * kBfBK, p);
+    load_b(kbeg);
+    store_b(0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
+      const bool more = k0 + kBfBK < kend;
+      if (k0 + PDA * kBfBK < kend) load_a(k0 + PDA * kBfBK, PDA);
+      if (more) load_b(k0 + kBfBK);
+#pragma unroll
+      for (int tn = 0; tn < TN; ++tn) {
+        const bf8v b = *reinterpret_cast<const bf8v *>(&sB[buf][bcol + tn * 16 + r16][g8]);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), b, acc[tm][tn]);
+      }
+      if (more) store_b(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+#pragma unroll
+      for (int p = 0; p < PDA; ++p)
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) ah[p][tm] = ah[p + 1][tm];
+    }
+  }
+  bf_epilogue<BM, BN, WM, WN, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
+}
+
 // Tile configurations of the split-K product (which = 0) and the point-row
 // product (1): rows BM x columns BN of a workgroup, staged (both operands
 // through LDS, k_gemm_bf) or direct (A from global memory, k_gemm_bfd).
 // Configuration 0 is valid for every padded shape (M % 64, N % 32).
 // Configurations 6 and 7 are for single-operand products only (terms = 1):
-// direct-A kernels whose waves form a 2 x 2 (4 x 2) grid, each wave 32 rows x
-// 224 columns (split-K 7: 112), so a workgroup covers all 448 plan columns of
-// a 441-plan batch (split-K 7: 224) and the dose block is read once per
-// product.
+// k_gemm_b1 with a 2 x 2 (4 x 2) wave grid, each wave 32 rows x 224 columns
+// (split-K 7: 112), so a workgroup covers all 448 plan columns of a 441-plan
+// batch (split-K 7: 224) and the dose block is read once per product.
 constexpr int kBfCfgCount = 8;
 struct BfCfg { int bm, bn; bool single_only; };
 static const BfCfg kBfCfgs[2][kBfCfgCount] = {
@@ -660,8 +761,8 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
   hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
                      K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
 #define BF_DW(TMv, TNv, WMv, WNv)                                                                  \
-  hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, WNv, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv * WNv), \
-                     0, s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
+  hipLaunchKernelGGL((k_gemm_b1<TMv, TNv, WMv, WNv, 3, MODE, DL>), grid, dim3(64 * WMv * WNv), 0, s, \
+                     A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
   if constexpr (MODE == 0) {
     switch (cfg) {
       case 0: BF_ST(64, 32, 2, 1, 2); break;
