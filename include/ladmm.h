@@ -272,10 +272,11 @@ int ladmm_batch_step_sizes(const ladmm_batch *b, double *rho);
 int ladmm_batch_tiles(const ladmm_batch *b, int32_t *gemm1, int32_t *gemm2);
 /* Pin the tile configurations (no autotuning), for reproducible benchmarks.
  * An index that is not valid for the batch's shapes falls back to 0.
- * LADMM_E_INVALID for an index outside [0, 8) (the FP32 and FP64 products
- * have four configurations, the BF16 products eight, of which 6 and 7 cover
- * up to 448 plan columns per workgroup and serve LADMM_BF16's single-operand
- * products only; its refresh then runs the pair products in configuration 0). */
+ * LADMM_E_INVALID for an index outside [0, 10) (the FP32 and FP64 products
+ * have four configurations, the BF16 products ten, of which 6 to 9 (a
+ * ring-pipelined kernel of 64-, 112-, 96- and 448-column tiles) serve
+ * LADMM_BF16's single-operand products only; its refresh then runs the pair
+ * products in configuration 0). */
 int ladmm_batch_set_tiles(ladmm_batch *b, int32_t gemm1, int32_t gemm2);
 /* Launch mode of the iterations of the stacked plans (end of Sec. 2.B).  With
  * graphs on (the default) the kernel launches of a run chunk (check_every

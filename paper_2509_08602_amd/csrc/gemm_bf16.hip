@@ -44,6 +44,8 @@ namespace ladmm {
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+// 16 bytes of operand as a plain vector (register rings of loads stay in VGPRs)
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4v mfma_bf(bf8v a, bf8v b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -129,6 +131,7 @@ constexpr size_t bf_red_bytes() {
 }
 
 __device__ __forceinline__ bf8v as_bf8(uint4 u) { return __builtin_bit_cast(bf8v, u); }
+__device__ __forceinline__ bf8v as_bf8(u4v u) { return __builtin_bit_cast(bf8v, u); }
 
 __device__ __forceinline__ uint2 pack4(const uint16_t (&v)[4]) {
   return uint2{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16)};
@@ -143,6 +146,15 @@ __device__ __forceinline__ uint2 pack4(const uint16_t (&v)[4]) {
 // the 4 lanes of a column, and the two tiles of each 32-row block are added
 // (one partial per 32-row block).  `smem` must hold bf_red_bytes and no wave
 // may still read operand tiles from it.
+// Waves per SIMD the registers of a pair-product kernel must allow: two up to
+// 16 accumulator tiles per wave (the batched epilogue would otherwise take
+// enough registers to halve the occupancy), else one.
+constexpr int bf_min_waves(int tm, int tn) { return tm * tn <= 16 ? 2 : 1; }
+
+// Tiles per batch of the point-row epilogue (the last batch may be shorter):
+// fewer where the accumulators already take most of the registers.
+constexpr int bf_epi_batch(int tm, int tn) { return tm * tn >= 28 ? 2 : tn < 4 ? tn : 4; }
+
 template <int BM, int BN, int WM, int WN, int MODE, int DL>
 __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 * WN)],
                                             unsigned char *smem, int tid, int mt, int m0, int n0,
@@ -180,9 +192,11 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
   auto swh = reinterpret_cast<uint16_t (*)[LDW]>(smem + bf_stat_bytes<BM, BN, MODE>());
   auto swl = reinterpret_cast<uint16_t (*)[LDW]>(smem + bf_stat_bytes<BM, BN, MODE>() +
                                                   sizeof(uint16_t) * BN * LDW);
-  // per-row (group, sign) and per-column (1/rho, active) values, loaded once
+  // per-row (group, sign, whether its bound follows the low-dose mask) and
+  // per-column (1/rho, active) values, loaded once
   int grow[TM][4];
   float srow[TM][4];
+  bool lrow[TM][4];
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
@@ -190,6 +204,7 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
       const int m = m0 + wm * TM * 16 + tm * 16 + 4 * (lane >> 4) + r;
       grow[tm][r] = ea.pt.grp[m];
       srow[tm][r] = ea.pt.sig[m];
+      lrow[tm][r] = ea.pt.mask != nullptr && ea.pt.is_ld[grow[tm][r]] != 0;
     }
   float irc[TN];
   bool act[TN];
@@ -199,123 +214,157 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
     irc[tn] = MODE == EPI_OBJ ? 0.f : (float)ea.invrho[n];
     act[tn] = MODE == EPI_OBJ ? false : ea.active[n] != 0;
   }
+  // Tiles go in batches of NB: every load of a batch (q, the references and the
+  // bounds u) is issued before any of its stores.  Loads and stores share one
+  // counter, and once both are in flight a wait is a wait for all of them, so
+  // interleaving them per tile would cost a memory round trip per tile.
+  constexpr int NB = bf_epi_batch(TM, TN);
+  float qv4[NB][4], xr4[NB][4], wr4[NB][4], uu4[NB][4];
+  uint64_t mw[NB];
 #pragma unroll
   for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-      const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
-      const int mb = m0 + wm * TM * 16 + tm * 16 + 4 * (lane >> 4);
-      double st[NST];
-#pragma unroll
-      for (int q = 0; q < NST; ++q) st[q] = 0.0;
-      uint16_t wh[4] = {0, 0, 0, 0}, wl[4] = {0, 0, 0, 0}, dw[4] = {0, 0, 0, 0};
-      float qv4[4], xr4[4], wr4[4];
+    for (int tb = 0; tb < TN; tb += NB) {
       if (MODE != EPI_OBJ) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const size_t o = (size_t)(mb + r) * ea.ldq + n;
-          qv4[r] = ea.q[o];
-          if (kDeltaIn) xr4[r] = ea.xref[o];
-          if (DL == BF_DELTA) wr4[r] = ea.wref[o];
+        for (int b = 0; b < NB; ++b) {
+          if (tb + b >= TN) break;
+          const int n = n0 + wn * TN * 16 + (tb + b) * 16 + (lane & 15);
+          const int mb = m0 + wm * TM * 16 + tm * 16 + 4 * (lane >> 4);
+          // the low-dose mask word of rows mb .. mb + 3 (one 64-row block)
+          mw[b] = ea.pt.mask != nullptr ? ea.pt.mask[(size_t)n * ea.pt.mask_words + (mb >> 6)] : ~0ull;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const size_t o = (size_t)(mb + r) * ea.ldq + n;
+            uu4[b][r] = ea.pt.utab[(size_t)grow[tm][r] * ea.pt.ldu + n];
+            qv4[b][r] = ea.q[o];
+            if (kDeltaIn) xr4[b][r] = ea.xref[o];
+            if (DL == BF_DELTA) wr4[b][r] = ea.wref[o];
+          }
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        const int g = grow[tm][r];
-        const float sg = srow[tm][r];
-        const float u = upper_bf(ea.pt, g, m, n);
-        float s = acc[tm][tn][r];
-        if (kDeltaIn) s = xr4[r] + s;
-        if (MODE == EPI_OBJ) {
-          if (ea.pt.is_oar[g]) {
-            st[1] = fmax(st[1], (double)(-s));
+      for (int b = 0; b < NB; ++b) {
+        const int tn = tb + b;
+        if (tn >= TN) break;
+        const int n = n0 + wn * TN * 16 + tn * 16 + (lane & 15);
+        const int mb = m0 + wm * TM * 16 + tm * 16 + 4 * (lane >> 4);
+        double st[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) st[q] = 0.0;
+        uint16_t wh[4] = {0, 0, 0, 0}, wl[4] = {0, 0, 0, 0}, dw[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = mb + r;
+          const int g = grow[tm][r];
+          const float sg = srow[tm][r];
+          // upper_bf from the values of the load phase
+          const float u = MODE == EPI_OBJ                                ? upper_bf(ea.pt, g, m, n)
+                          : lrow[tm][r] && !((mw[b] >> (m & 63)) & 1ull) ? 0.f
+                                                                         : uu4[b][r];
+          float s = acc[tm][tn][r];
+          if (kDeltaIn) s = xr4[b][r] + s;
+          if (MODE == EPI_OBJ) {
+            if (ea.pt.is_oar[g]) {
+              st[1] = fmax(st[1], (double)(-s));
+            } else {
+              const double h = fmax(0.0, (double)sg - (double)s);
+              st[0] = fma((double)u, h, st[0]);
+              if (sg > 0.f) st[2] = fma((double)u, (double)s, st[2]);
+            }
           } else {
-            const double h = fmax(0.0, (double)sg - (double)s);
-            st[0] = fma((double)u, h, st[0]);
-            if (sg > 0.f) st[2] = fma((double)u, (double)s, st[2]);
-          }
-        } else {
-          const float qv = qv4[r];
-          const float z = clip0u_f(qv, u);
-          float wref = 0.f;
-          if (DL == BF_DELTA) wref = wr4[r];
-          if (DL == BF_REFRESH) {
-            // the references of the running plans (a frozen plan keeps those
-            // of its last refresh, consistent with its G_ref and v_ref, which
-            // are recorded for running plans only too)
-            uint16_t h, l;
-            split_pair((double)(2.f * z - qv), h, l);   // the pairs the refresh's GEMM1 read
-            wref = pair_val(h, l);
-            if (act[tn]) {
-              const size_t o = (size_t)m * ea.ldq + n;
-              ea.xref[o] = s;
-              ea.wref[o] = wref;
+            const float qv = qv4[b][r];
+            const float z = clip0u_f(qv, u);
+            float wref = 0.f;
+            if (DL == BF_DELTA) wref = wr4[b][r];
+            if (DL == BF_REFRESH) {
+              // the references of the running plans (a frozen plan keeps those
+              // of its last refresh, consistent with its G_ref and v_ref, which
+              // are recorded for running plans only too)
+              uint16_t h, l;
+              split_pair((double)(2.f * z - qv), h, l);   // the pairs the refresh's GEMM1 read
+              wref = pair_val(h, l);
+              if (act[tn]) {
+                const size_t o = (size_t)m * ea.ldq + n;
+                ea.xref[o] = s;
+                ea.wref[o] = wref;
+              }
+            }
+            const float qx = z + sg * irc[tn] - s;   // x + y of the closed-form x-step
+            // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
+            const float qn = ea.alpha == 1.0 ? qx : qv + (float)ea.alpha * (qx - qv);
+            const float wv = 2.f * clip0u_f(qn, u) - qn;
+            if (kPairsOut) split_pair((double)wv, wh[r], wl[r]);
+            if (kDwOut) dw[r] = bf_round(wv - wref);
+            if (act[tn]) ea.q[(size_t)m * ea.ldq + n] = qn;
+            if (MODE == EPI_ADMM_STATS) {
+              const double yo = (double)qv - (double)z;
+              const double zn = (double)clip0u_f(qn, u);
+              const double yn = (double)qn - zn;
+              const double x = (double)qx - yo;
+              // x - z' (the unrelaxed x); without relaxation y' - y is the same value
+              const double dxz = ea.alpha == 1.0 ? yn - yo : x - zn, dz = zn - (double)z;
+              st[0] = fma(dxz, dxz, st[0]);
+              st[1] = fma(x, x, st[1]);
+              st[2] = fma(zn, zn, st[2]);
+              st[3] = fma(dz, dz, st[3]);
+              st[4] = fma(yn, yn, st[4]);
+              st[5] = fma(-(double)sg, zn, st[5]);
             }
           }
-          const float qx = z + sg * irc[tn] - s;   // x + y of the closed-form x-step
-          // over-relaxed: x_hat + y = alpha (x + y) + (1 - alpha) (z + y)
-          const float qn = ea.alpha == 1.0 ? qx : qv + (float)ea.alpha * (qx - qv);
-          const float wv = 2.f * clip0u_f(qn, u) - qn;
-          if (kPairsOut) split_pair((double)wv, wh[r], wl[r]);
-          if (kDwOut) dw[r] = bf_round(wv - wref);
-          if (act[tn]) ea.q[(size_t)m * ea.ldq + n] = qn;
-          if (MODE == EPI_ADMM_STATS) {
-            const double yo = (double)qv - (double)z;
-            const double zn = (double)clip0u_f(qn, u);
-            const double yn = (double)qn - zn;
-            const double x = (double)qx - yo;
-            // x - z' (the unrelaxed x); without relaxation y' - y is the same value
-            const double dxz = ea.alpha == 1.0 ? yn - yo : x - zn, dz = zn - (double)z;
-            st[0] = fma(dxz, dxz, st[0]);
-            st[1] = fma(x, x, st[1]);
-            st[2] = fma(zn, zn, st[2]);
-            st[3] = fma(dz, dz, st[3]);
-            st[4] = fma(yn, yn, st[4]);
-            st[5] = fma(-(double)sg, zn, st[5]);
-          }
         }
-      }
-      if (bf_wstaged<BM, BN, MODE, DL>()) {
-        // staged: column n - n0, rows mb - m0 .. + 3
-        const int cl = n - n0, rl = mb - m0;
-        if (DL == BF_DELTA) {
-          *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(dw);
-        } else {
-          *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(wh);
-          *reinterpret_cast<uint2 *>(&swl[cl][rl]) = pack4(wl);
-        }
-      } else if (MODE != EPI_OBJ && act[tn]) {
-        const size_t o = (size_t)n * ea.ldwt + mb;
-        if (kPairsOut) {
-          *reinterpret_cast<uint2 *>(ea.wt_hi + o) = pack4(wh);
-          *reinterpret_cast<uint2 *>(ea.wt_lo + o) = pack4(wl);
-        }
-        if (kDwOut) *reinterpret_cast<uint2 *>(ea.dw + o) = pack4(dw);
-      }
-      if (kStats) {
-#pragma unroll
-        for (int q = 0; q < NST; ++q) {
-          double v = st[q];
-          if (MODE == EPI_OBJ && q == 1) {
-            v = fmax(v, __shfl_xor(v, 16));
-            v = fmax(v, __shfl_xor(v, 32));
+        if (bf_wstaged<BM, BN, MODE, DL>()) {
+          // staged: column n - n0, rows mb - m0 .. + 3
+          const int cl = n - n0, rl = mb - m0;
+          if (DL == BF_DELTA) {
+            *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(dw);
           } else {
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
+            *reinterpret_cast<uint2 *>(&swh[cl][rl]) = pack4(wh);
+            *reinterpret_cast<uint2 *>(&swl[cl][rl]) = pack4(wl);
           }
-          if (lane < 16) sred[wm * TM + tm][q][wn * TN * 16 + tn * 16 + lane] = v;
+        } else if (MODE != EPI_OBJ && act[tn]) {
+          const size_t o = (size_t)n * ea.ldwt + mb;
+          if (kPairsOut) {
+            *reinterpret_cast<uint2 *>(ea.wt_hi + o) = pack4(wh);
+            *reinterpret_cast<uint2 *>(ea.wt_lo + o) = pack4(wl);
+          }
+          if (kDwOut) *reinterpret_cast<uint2 *>(ea.dw + o) = pack4(dw);
+        }
+        if (kStats) {
+#pragma unroll
+          for (int q = 0; q < NST; ++q) {
+            double v = st[q];
+            if (MODE == EPI_OBJ && q == 1) {
+              v = fmax(v, __shfl_xor(v, 16));
+              v = fmax(v, __shfl_xor(v, 32));
+            } else {
+              v += __shfl_xor(v, 16);
+              v += __shfl_xor(v, 32);
+            }
+            if (lane < 16) sred[wm * TM + tm][q][wn * TN * 16 + tn * 16 + lane] = v;
+          }
         }
       }
     }
   if (MODE == EPI_OBJ && !kStats) return;
   __syncthreads();
   if (bf_wstaged<BM, BN, MODE, DL>()) {
-    // W' (or dW) of the active plans: each column's BM rows as 16-byte pieces, in order
-    for (int e = tid; e < BN * (BM / 8); e += NT) {
+    // W' (or dW) of the active plans: each column's BM rows as 16-byte pieces,
+    // in order (the column flags are read before the first store)
+    constexpr int NW = (BN * (BM / 8) + NT - 1) / NT;
+    static_assert(NW <= 32, "one flag bit per piece");
+    uint32_t wact = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int e = tid + i * NT;
+      if (e < BN * (BM / 8) && ea.active[n0 + e / (BM / 8)] != 0) wact |= 1u << i;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int e = tid + i * NT;
+      if (!((wact >> i) & 1u)) continue;
       const int cl = e / (BM / 8), ch = (e % (BM / 8)) * 8;
       const int n = n0 + cl;
-      if (!ea.active[n]) continue;
       const size_t o = (size_t)n * ea.ldwt + m0 + ch;
       if (DL == BF_DELTA) {
         *reinterpret_cast<uint4 *>(ea.dw + o) = *reinterpret_cast<const uint4 *>(&swh[cl][ch]);
@@ -339,7 +388,8 @@ __device__ __forceinline__ void bf_epilogue(f4v (&acc)[BM / (16 * WM)][BN / (16 
 // the LDS, so more workgroups per CU), the next stage waiting in registers
 // behind a barrier.
 template <int BM, int BN, int WM, int WN, int TERMS, int MODE, int NBUF, int DL>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, int K, int kchunk,
+__global__ __launch_bounds__(64 * WM * WN, bf_min_waves(BM / (16 * WM), BN / (16 * WN))) void k_gemm_bf(
+    BfPair A, BfPair B, int K, int kchunk,
                                                          int mtiles, int ntiles,
                                                          float *__restrict__ P, int ldp,
                                                          size_t pstride, EpiArgs<float> ea) {
@@ -495,7 +545,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bf(BfPair A, BfPair B, in
 // of a fragment hits the cache) and each wave reads only its own TN column
 // tiles of B from LDS.
 template <int TM, int TN, int WM, int WN, int PD, int TERMS, int MODE, int DL>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_bfd(BfPair A, BfPair B, int K, int kchunk,
+__global__ __launch_bounds__(64 * WM * WN, bf_min_waves(TM, TN)) void k_gemm_bfd(
+    BfPair A, BfPair B, int K, int kchunk,
                                                            int mtiles, int ntiles,
                                                            float *__restrict__ P, int ldp,
                                                            size_t pstride, EpiArgs<float> ea) {
@@ -624,23 +675,35 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_bfd(BfPair A, BfPair B, i
 
 // Single-operand products (terms = 1, LADMM_BF16's hot iterations).  With one
 // MFMA per accumulator and k step, a step's MFMA work (TM TN per wave) is a
-// third of the pair products', too short to hide a dose-block fetch from HBM
-// behind one stage of prefetch.  Here the A fragments (the dose block, read
-// once per product) run PDA k steps ahead in a register ring, and B (the small
-// plan-side operand, served by L2) one step ahead through two LDS stages; each
-// B fragment is read from LDS right before the TM MFMAs that use it.  The waves
-// form a WM x WN grid (a workgroup spans up to all plan columns).  Every
-// accumulator takes one MFMA per k step in k order, as in the other kernels,
-// so the results are the same bits.
-template <int TM, int TN, int WM, int WN, int PDA, int MODE, int DL>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_b1(BfPair A, BfPair B, int K, int kchunk,
+// third of the pair products', far too short to hide a fetch from HBM behind
+// one step of prefetch.  Here both operands run kRing k steps ahead in
+// register rings: the A fragments (the dose block, read once per product)
+// straight from global memory, and B (the small plan-side operand, served by
+// L2) on its way to one of two LDS stages.  Vector loads retire in issue order,
+// so a wait for one load is a wait for every older one: the rings are indexed
+// by step modulo kRing with the loop unrolled kRing times (no register copies
+// that would wait for a load in flight), and every load in the unrolled body is
+// issued unconditionally (addresses past the last step are clamped to it and
+// the data is never used), so that the compiler's waits name exact counts and
+// about kRing - 1 steps of loads stay in flight.  Per step: the B load of step
+// t + kRing goes out first, then the MFMAs of step t (each B fragment read from
+// LDS right before its TM MFMAs), then the A load of step t + kRing into the
+// slot just used, and the LDS store of B for step t + 1.  The waves form a
+// WM x WN grid (a workgroup spans up to all plan columns).  Every accumulator
+// takes one MFMA per k step in k order, as in the other kernels, so the results
+// are the same bits.  OCC: waves per SIMD the registers must allow.
+// (kend - kbeg) % 32 == 0.
+constexpr int kRing = 4;
+
+template <int TM, int TN, int WM, int WN, int OCC, int MODE, int DL>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair B, int K, int kchunk,
                                                           int mtiles, int ntiles,
                                                           float *__restrict__ P, int ldp,
                                                           size_t pstride, EpiArgs<float> ea) {
   constexpr int BM = TM * 16 * WM, BN = TN * 16 * WN, NT = 64 * WM * WN;
   constexpr int KV = kBfBK / 8;
   constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
-  static_assert(PDA >= 1, "prefetch distance");
+  static_assert(kRing % 2 == 0, "the LDS stage of step t is t % 2 = (t % kRing) % 2");
   static_assert(MODE == 0 || (TM * 16) % 32 == 0, "statistics partials are per 32-row block");
   constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
   constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE, DL>();
@@ -655,6 +718,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_b1(BfPair A, BfPair B, in
   const int m0 = mt * BM, n0 = nt * BN;
   const int kbeg = MODE == 0 ? zc * kchunk : 0;
   const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
+  const int nsteps = kend > kbeg ? (kend - kbeg) / kBfBK : 0;
   const int g8 = 8 * (lane >> 4), r16 = lane & 15;
   const int bcol = wn * TN * 16;
 
@@ -664,61 +728,72 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_b1(BfPair A, BfPair B, in
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
 
-  const size_t arow = frag_off(m0 + wm * TM * 16, 0, A.ld) + (size_t)lane * 8;
+  // this lane's piece of the first A fragment of the chunk, and per B element
+  // slot its row and k offset (slots past BV load element BV - 1 again and are
+  // not stored)
+  const uint16_t *abase = A.hi + frag_off(m0 + wm * TM * 16, kbeg, A.ld) + (size_t)lane * 8;
   const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
-  uint4 ah[PDA + 1][TM], rb[BVT];
-  auto load_a = [&](int k0, int slot) {
-    const bool in = k0 + g8 < kend;
+  const uint16_t *bbase[BVT];
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm) {
-      const size_t off = arow + tm * astep + (size_t)(k0 >> 5) * 512;
-      ah[slot][tm] = in ? *reinterpret_cast<const uint4 *>(A.hi + off) : uint4{0, 0, 0, 0};
-    }
+  for (int i = 0; i < BVT; ++i) {
+    const int e = min(tid + i * NT, BV - 1);
+    bbase[i] = B.hi + (size_t)(n0 + e / KV) * B.ld + kbeg + (e % KV) * 8;
+  }
+  u4v ah[kRing][TM], rb[kRing][BVT];
+  auto load_a = [&](int t, u4v (&dst)[TM]) {
+    const size_t ko = (size_t)min(t, nsteps - 1) * 512;
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm) dst[tm] = *reinterpret_cast<const u4v *>(abase + tm * astep + ko);
   };
-  auto load_b = [&](int k0) {
+  auto load_b = [&](int t, u4v (&dst)[BVT]) {
+    const int ko = min(t, nsteps - 1) * kBfBK;
+#pragma unroll
+    for (int i = 0; i < BVT; ++i) dst[i] = *reinterpret_cast<const u4v *>(bbase[i] + ko);
+  };
+  auto store_b = [&](const u4v (&src)[BVT], int stage) {
 #pragma unroll
     for (int i = 0; i < BVT; ++i) {
       const int e = tid + i * NT;
-      if (e < BV) {
-        const int row = e / KV, k = k0 + (e % KV) * 8;
-        const size_t off = (size_t)(n0 + row) * B.ld + k;
-        rb[i] = k < kend ? *reinterpret_cast<const uint4 *>(B.hi + off) : uint4{0, 0, 0, 0};
-      }
+      if (BV % NT == 0 || e < BV) *reinterpret_cast<u4v *>(&sB[stage][e / KV][(e % KV) * 8]) = src[i];
     }
   };
-  auto store_b = [&](int buf) {
+  auto mma = [&](const u4v (&a)[TM], int stage) {
 #pragma unroll
-    for (int i = 0; i < BVT; ++i) {
-      const int e = tid + i * NT;
-      if (e < BV) *reinterpret_cast<uint4 *>(&sB[buf][e / KV][(e % KV) * 8]) = rb[i];
+    for (int tn = 0; tn < TN; ++tn) {
+      const bf8v b = *reinterpret_cast<const bf8v *>(&sB[stage][bcol + tn * 16 + r16][g8]);
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) acc[tm][tn] = mfma_bf(as_bf8(a[tm]), b, acc[tm][tn]);
     }
   };
 
-  if (kbeg < kend) {
+  if (nsteps > 0) {
 #pragma unroll
-    for (int p = 0; p < PDA; ++p)
-      if (kbeg + p * kBfBK < kend) load_a(kbeg + p * kBfBK, p);
-    load_b(kbeg);
-    store_b(0);
+    for (int p = 0; p < kRing; ++p) {
+      load_b(p, rb[p]);
+      load_a(p, ah[p]);
+    }
+    store_b(rb[0], 0);
     __syncthreads();
-    int buf = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += kBfBK) {
-      const bool more = k0 + kBfBK < kend;
-      if (k0 + PDA * kBfBK < kend) load_a(k0 + PDA * kBfBK, PDA);
-      if (more) load_b(k0 + kBfBK);
+    int t0 = 0;
+    for (; t0 + kRing <= nsteps; t0 += kRing) {
 #pragma unroll
-      for (int tn = 0; tn < TN; ++tn) {
-        const bf8v b = *reinterpret_cast<const bf8v *>(&sB[buf][bcol + tn * 16 + r16][g8]);
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm) acc[tm][tn] = mfma_bf(as_bf8(ah[0][tm]), b, acc[tm][tn]);
+      for (int i = 0; i < kRing; ++i) {
+        const int t = t0 + i;
+        load_b(t + kRing, rb[i]);           // B of step t left rb[i] for LDS at step t - 1
+        mma(ah[i], i & 1);
+        load_a(t + kRing, ah[i]);
+        store_b(rb[(i + 1) % kRing], (i + 1) & 1);   // past the last step: never read
+        __syncthreads();
       }
-      if (more) store_b(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+    }
+    // the last nsteps % kRing steps: their operands are already loaded
 #pragma unroll
-      for (int p = 0; p < PDA; ++p)
-#pragma unroll
-        for (int tm = 0; tm < TM; ++tm) ah[p][tm] = ah[p + 1][tm];
+    for (int i = 0; i < kRing - 1; ++i) {
+      if (t0 + i < nsteps) {
+        mma(ah[i], i & 1);
+        store_b(rb[(i + 1) % kRing], (i + 1) & 1);
+        __syncthreads();
+      }
     }
   }
   bf_epilogue<BM, BN, WM, WN, MODE, DL>(acc, smem, tid, mt, m0, n0, zc, P, ldp, pstride, ea);
@@ -728,17 +803,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_b1(BfPair A, BfPair B, in
 // product (1): rows BM x columns BN of a workgroup, staged (both operands
 // through LDS, k_gemm_bf) or direct (A from global memory, k_gemm_bfd).
 // Configuration 0 is valid for every padded shape (M % 64, N % 32).
-// Configurations 6 and 7 are for single-operand products only (terms = 1):
-// k_gemm_b1 with a 2 x 2 (4 x 2) wave grid, each wave 32 rows x 224 columns
-// (split-K 7: 112), so a workgroup covers all 448 plan columns of a 441-plan
-// batch (split-K 7: 224) and the dose block is read once per product.
-constexpr int kBfCfgCount = 8;
+// Configurations 6 to 9 are for single-operand products only (terms = 1,
+// K % 32 == 0), on k_gemm_b1: 4 waves of 48 (split-K) or 32 (point-row) rows
+// by 64, 112 and 96 columns, so that every launch width of a compacted run (a
+// multiple of 64, 96 or 224) has one, and 8 waves of 32 x 112 (split-K) or
+// 32 x 224 (point-row) that cover all 448 plan columns of a 441-plan batch.
+constexpr int kBfCfgCount = 10;
 struct BfCfg { int bm, bn; bool single_only; };
 static const BfCfg kBfCfgs[2][kBfCfgCount] = {
     {{64, 32, false}, {64, 64, false}, {192, 112, false}, {160, 112, false}, {64, 96, false},
-     {192, 64, false}, {64, 448, true}, {64, 224, true}},
+     {192, 64, false}, {192, 64, true}, {192, 112, true}, {192, 96, true}, {64, 448, true}},
     {{64, 32, false}, {256, 64, false}, {128, 112, false}, {128, 112, false}, {128, 96, false},
-     {128, 64, false}, {128, 448, true}, {64, 448, true}}};
+     {128, 64, false}, {128, 64, true}, {128, 112, true}, {128, 96, true}, {128, 448, true}}};
 
 bool gemm_bf_cfg_ok(int which, int cfg, int M, int N, int terms) {
   if (cfg < 0 || cfg >= kBfCfgCount) return false;
@@ -760,8 +836,8 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
 #define BF_DI(TMv, TNv, WMv)                                                                       \
   hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
                      K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
-#define BF_DW(TMv, TNv, WMv, WNv)                                                                  \
-  hipLaunchKernelGGL((k_gemm_b1<TMv, TNv, WMv, WNv, 3, MODE, DL>), grid, dim3(64 * WMv * WNv), 0, s, \
+#define BF_DW(TMv, TNv, WMv, WNv, OCCv)                                                            \
+  hipLaunchKernelGGL((k_gemm_b1<TMv, TNv, WMv, WNv, OCCv, MODE, DL>), grid, dim3(64 * WMv * WNv), 0, s, \
                      A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
   if constexpr (MODE == 0) {
     switch (cfg) {
@@ -772,10 +848,16 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(1, 6, 4); break;
       case 5: BF_DI(3, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_DW(2, 14, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(3, 4, 4, 1, 3); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_DW(2, 7, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(3, 7, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 8:
+        if constexpr (TERMS == 1) { BF_DW(3, 6, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 9:
+        if constexpr (TERMS == 1) { BF_DW(2, 7, 2, 4, 2); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
@@ -788,10 +870,16 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(2, 6, 4); break;
       case 5: BF_DI(2, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_DW(2, 14, 4, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 4, 4, 1, 3); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_DW(2, 14, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 7, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 8:
+        if constexpr (TERMS == 1) { BF_DW(2, 6, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        break;
+      case 9:
+        if constexpr (TERMS == 1) { BF_DW(2, 14, 4, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
@@ -804,7 +892,7 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
 
 hipError_t gemm_bf_tn(hipStream_t s, BfPair A, BfPair B, float *P, int ldp, int M, int N, int K,
                       int nchunk, int terms, int cfg) {
-  if (!gemm_bf_cfg_ok(0, cfg, M, N, terms)) cfg = 0;
+  if (!gemm_bf_cfg_ok(0, cfg, M, N, terms) || (kBfCfgs[0][cfg].single_only && K % kBfBK)) cfg = 0;
   if (!gemm_bf_cfg_ok(0, cfg, M, N, terms) || nchunk < 1 || K % 8 || A.ld % 8 || B.ld % 8)
     return hipErrorInvalidValue;
   int kchunk = (K + nchunk - 1) / nchunk;
@@ -972,46 +1060,60 @@ hipError_t shot_scaled_bf(hipStream_t s, const SmallArgs &a, const double *q2, u
   return hipGetLastError();
 }
 
-__global__ void k_w_from_q_bf(const float *__restrict__ q, int Np, int kp, PointTable<float> pt,
-                              uint16_t *__restrict__ wh, uint16_t *__restrict__ wl,
-                              const float *__restrict__ wref, uint16_t *__restrict__ dw) {
-  const size_t total = (size_t)Np * kp;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int p = (int)(e / kp), j = (int)(e % kp);
-    const float qv = q[e];
-    const float w = 2.f * clip0u_f(qv, upper_bf(pt, pt.grp[p], p, j)) - qv;
-    uint16_t h, l;
-    split_pair((double)w, h, l);
-    wh[(size_t)j * Np + p] = h;
-    wl[(size_t)j * Np + p] = l;
-    if (dw != nullptr) dw[(size_t)j * Np + p] = bf_round(w - wref[e]);
+// Point-major FP32 values of q -> plan-major BF16 rows, through a 64 x 64 LDS
+// tile so that both the reads (plans contiguous) and the writes (points
+// contiguous) are coalesced.  KIND 0: z1 = clip(q, 0, u) as pairs; KIND 1:
+// W = 2 clip(q, 0, u) - q as pairs and, with dw, dW = bf16(W - W_ref).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_plan_major_bf(const float *__restrict__ q, int Np, int kp,
+                                                       PointTable<float> pt,
+                                                       uint16_t *__restrict__ hi,
+                                                       uint16_t *__restrict__ lo,
+                                                       const float *__restrict__ wref,
+                                                       uint16_t *__restrict__ dw) {
+  __shared__ uint16_t sh[64][66], sl[64][66], sd[64][66];   // [plan][point]
+  const int p0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int pp = i >> 6, jj = i & 63;
+    const int p = p0 + pp, j = j0 + jj;
+    uint16_t h = 0, l = 0, d = 0;
+    if (p < Np && j < kp) {
+      const size_t e = (size_t)p * kp + j;
+      const float qv = q[e];
+      const float z = clip0u_f(qv, upper_bf(pt, pt.grp[p], p, j));
+      const float v = KIND == 0 ? z : 2.f * z - qv;
+      split_pair((double)v, h, l);
+      if (KIND == 1 && dw != nullptr) d = bf_round(v - wref[e]);
+    }
+    sh[jj][pp] = h;
+    sl[jj][pp] = l;
+    sd[jj][pp] = d;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int jj = i >> 6, pp = i & 63;
+    const int p = p0 + pp, j = j0 + jj;
+    if (p < Np && j < kp) {
+      const size_t o = (size_t)j * Np + p;
+      hi[o] = sh[jj][pp];
+      lo[o] = sl[jj][pp];
+      if (KIND == 1 && dw != nullptr) dw[o] = sd[jj][pp];
+    }
   }
 }
 
 hipError_t w_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
                        uint16_t *wh, uint16_t *wl, const float *wref, uint16_t *dw) {
-  hipLaunchKernelGGL(k_w_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, wh, wl, wref, dw);
+  hipLaunchKernelGGL(k_plan_major_bf<1>, dim3((Np + 63) / 64, (kp + 63) / 64), dim3(256), 0, s, q, Np,
+                     kp, pt, wh, wl, wref, dw);
   return hipGetLastError();
 }
 
 // z1 = clip(q, 0, u) as plan-major pairs: the certificate's product operand.
-__global__ void k_z_from_q_bf(const float *__restrict__ q, int Np, int kp, PointTable<float> pt,
-                              uint16_t *__restrict__ zh, uint16_t *__restrict__ zl) {
-  const size_t total = (size_t)Np * kp;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int p = (int)(e / kp), j = (int)(e % kp);
-    uint16_t h, l;
-    split_pair((double)clip0u_f(q[e], upper_bf(pt, pt.grp[p], p, j)), h, l);
-    zh[(size_t)j * Np + p] = h;
-    zl[(size_t)j * Np + p] = l;
-  }
-}
-
 hipError_t z_from_q_bf(hipStream_t s, const float *q, int Np, int kp, const PointTable<float> &pt,
                        uint16_t *zh, uint16_t *zl) {
-  hipLaunchKernelGGL(k_z_from_q_bf, dim3(2048), dim3(256), 0, s, q, Np, kp, pt, zh, zl);
+  hipLaunchKernelGGL(k_plan_major_bf<0>, dim3((Np + 63) / 64, (kp + 63) / 64), dim3(256), 0, s, q, Np,
+                     kp, pt, zh, zl, nullptr, nullptr);
   return hipGetLastError();
 }
 

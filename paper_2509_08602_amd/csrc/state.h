@@ -19,7 +19,7 @@ namespace ladmm {
 
 // Tile configurations per dose-matrix product in the largest table (the
 // BF16-pair kernels; the FP32 / FP64 tables have kGemmCfgs and reject the rest).
-constexpr int kMaxGemmCfgs = 8;
+constexpr int kMaxGemmCfgs = 10;
 
 // Message of the last error on the calling thread (ladmm_last_error).
 extern thread_local std::string g_err;

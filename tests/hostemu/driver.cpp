@@ -87,6 +87,11 @@ int main(int argc, char **argv) {
   CHECK(ladmm_batch_create(cs, k, w.data(), use_mask ? mask.data() : nullptr, nullptr, &o, &b));
   if (tile1 >= 0) CHECK(ladmm_batch_set_tiles(b, tile1, tile2));
   CHECK(ladmm_batch_iterate(b, iters));
+  {
+    int32_t used[2] = {-1, -1};
+    CHECK(ladmm_batch_tiles(b, &used[0], &used[1]));
+    save(dir + "/tiles.i32", used, 2);
+  }
   std::vector<double> z1((size_t)n_A * k), y1((size_t)n_A * k), z2((size_t)m_A * k), y2((size_t)m_A * k);
   CHECK(ladmm_batch_export(b, z1.data(), y1.data(), z2.data(), y2.data()));
   save(dir + "/z1.f64", z1.data(), z1.size());

@@ -347,7 +347,7 @@ def test_tile_configurations_give_identical_results(ctx, c0, precision):
     ncfg = 4
     if precision in ("bf16x3", "bf16"):
         plan_sets += [cases.config_weights(1), cases.config_weights(2)]
-        ncfg = 8
+        ncfg = 10
     for w in plan_sets:
         ref, used = None, set()
         for c1 in range(ncfg):

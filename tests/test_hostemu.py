@@ -122,10 +122,13 @@ ITER_CASES = [("f64", 1e-11, (0, 0), 0, 5),
               # iterates carry BF16 rounding (2^-9 relative per operand) until
               # the refresh that ends the chunk
               ("bf16", 3e-2, (-1, -1), 12, 5),
-              # the single-operand tiles whose waves split rows and columns, a
-              # workgroup spanning 224 or 448 plan columns
+              # the single-operand tiles of the ring-pipelined kernel: 64, 112
+              # and 96 plan columns per workgroup, and 448 (waves split rows
+              # and columns)
               ("bf16", 3e-2, (6, 6), 0, 448),
-              ("bf16", 3e-2, (7, 7), 0, 448)]
+              ("bf16", 3e-2, (7, 7), 0, 448),
+              ("bf16", 3e-2, (8, 8), 0, 96),
+              ("bf16", 3e-2, (9, 9), 0, 448)]
 
 
 # compaction runs: enough plans for the launched width to shrink (FP32 in
@@ -137,8 +140,17 @@ def _iter_name(precision, tiles, k):
     return f"iter-{precision}-{tiles[0]}{tiles[1]}-{k}"
 
 
-def _iter_spec(k):
+def _iter_spec(k, wide=False):
+    """wide: 8 isocentres (192 shot columns, 512 padded points), so that the
+    single-operand tiles of 192 shot rows and 128 point rows apply."""
+    if wide:
+        spec = cases.mini_spec(n_iso=8, sectors=8, collimators=3, radius=3.0, n_ring=90, n_ld=60)
+        return cases.build_case(spec, 1), cases.random_weights(k, 2)
     return small_case(1), cases.random_weights(k, 2)
+
+
+def _wide(tiles):
+    return tiles[0] >= 6
 
 
 def _mask_spec():
@@ -184,7 +196,7 @@ def _prepare(root):
     runs = {}
     for precision, _, tiles, solve, k in ITER_CASES:
         d = os.path.join(root, _iter_name(precision, tiles, k))
-        case, w = _iter_spec(k)
+        case, w = _iter_spec(k, _wide(tiles))
         write_inputs(d, case, w, precision, 4, solve_iters=solve, tiles=tiles)
         runs[_iter_name(precision, tiles, k)] = d
     m = _mask_spec()
@@ -220,7 +232,7 @@ def _prepare(root):
         write_inputs(d, case, w, precision, 1, tiles=(0, 0))
         runs["refresh-" + precision] = d
     for precision, k in COMPACT_CASES:
-        case, w = _iter_spec(k)
+        case, w = _iter_spec(k, precision == "bf16")
         d = os.path.join(root, f"compact-{precision}")
         write_inputs(d, case, w, precision, 1, tiles=(0, 0), compact_iters=12)
         runs[f"compact-{precision}"] = d
@@ -253,7 +265,9 @@ def test_emulated_iterations_match_oracle(emu, precision, tol, tiles, solve, k):
     BF16-pair products carry about 2^-16 relative error per product, of the
     order of the FP32 path's, hence the same kind of tolerance."""
     d = finished(emu, _iter_name(precision, tiles, k))
-    case, w = _iter_spec(k)
+    case, w = _iter_spec(k, _wide(tiles))
+    if tiles[0] >= 0:   # the pinned configurations are the ones that ran
+        assert np.fromfile(os.path.join(d, "tiles.i32"), np.int32).tolist() == list(tiles)
     iters = 4
     lp = olp.assemble(case, w)
     slp = olp.precondition(lp, olp.bot_scale(case))
@@ -416,7 +430,7 @@ def test_emulated_compaction_gives_identical_results(emu, precision, k):
     between checks, and without: the same bits for every plan, and plans that
     stopped at different checks."""
     d = finished(emu, f"compact-{precision}")
-    case, w = _iter_spec(k)
+    case, w = _iter_spec(k, precision == "bf16")
     n_A = case.n_points + case.n_iso * case.n_sectors
     it_on = np.fromfile(os.path.join(d, "compact_it_on.i32"), np.int32)
     it_off = np.fromfile(os.path.join(d, "compact_it_off.i32"), np.int32)
