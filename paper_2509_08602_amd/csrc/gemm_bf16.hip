@@ -676,40 +676,41 @@ __global__ __launch_bounds__(64 * WM * WN, bf_min_waves(TM, TN)) void k_gemm_bfd
 // Single-operand products (terms = 1, LADMM_BF16's hot iterations).  With one
 // MFMA per accumulator and k step, a step's MFMA work (TM TN per wave) is a
 // third of the pair products', far too short to hide a fetch from HBM behind
-// one step of prefetch.  Here both operands run kRing k steps ahead in
-// register rings: the A fragments (the dose block, read once per product)
-// straight from global memory, and B (the small plan-side operand, served by
-// L2) on its way to one of two LDS stages.  Vector loads retire in issue order,
-// so a wait for one load is a wait for every older one: the rings are indexed
-// by step modulo kRing with the loop unrolled kRing times (no register copies
-// that would wait for a load in flight), and every load in the unrolled body is
-// issued unconditionally (addresses past the last step are clamped to it and
-// the data is never used), so that the compiler's waits name exact counts and
-// about kRing - 1 steps of loads stay in flight.  Per step: the B load of step
-// t + kRing goes out first, then the MFMAs of step t (each B fragment read from
-// LDS right before its TM MFMAs), then the A load of step t + kRing into the
-// slot just used, and the LDS store of B for step t + 1.  The waves form a
+// one step of prefetch.  Here both operands run RING stages ahead in register
+// rings: the A fragments (the dose block, read once per product) straight from
+// global memory, and B (the small plan-side operand, served by L2) on its way
+// to one of two LDS stages.  A stage is KS MFMA k steps (one barrier per
+// stage).  Vector loads retire in issue order, so a wait for one load is a
+// wait for every older one: the rings are indexed by stage modulo RING with the
+// loop unrolled RING times (no register copies that would wait for a load in
+// flight), and every load in the unrolled body is issued unconditionally
+// (addresses past the last k step are clamped to it and the data is never
+// used), so that the compiler's waits name exact counts and about RING - 1
+// stages of loads stay in flight.  The last stage may hold fewer than KS k
+// steps; its MFMAs past the end are skipped.  Per stage: the B load of stage t + RING goes
+// out first, then the MFMAs of stage t, then the A load of stage t + RING into
+// the slot just used, and the LDS store of B for stage t + 1.  The waves form a
 // WM x WN grid (a workgroup spans up to all plan columns).  Every accumulator
 // takes one MFMA per k step in k order, as in the other kernels, so the results
 // are the same bits.  OCC: waves per SIMD the registers must allow.
 // (kend - kbeg) % 32 == 0.
-constexpr int kRing = 4;
-
-template <int TM, int TN, int WM, int WN, int OCC, int MODE, int DL>
+template <int TM, int TN, int WM, int WN, int OCC, int RING, int KS, int MODE, int DL>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair B, int K, int kchunk,
-                                                          int mtiles, int ntiles,
-                                                          float *__restrict__ P, int ldp,
-                                                          size_t pstride, EpiArgs<float> ea) {
+                                                               int mtiles, int ntiles,
+                                                               float *__restrict__ P, int ldp,
+                                                               size_t pstride, EpiArgs<float> ea) {
   constexpr int BM = TM * 16 * WM, BN = TN * 16 * WN, NT = 64 * WM * WN;
-  constexpr int KV = kBfBK / 8;
-  constexpr int BV = BN * KV, BVT = (BV + NT - 1) / NT;
-  static_assert(kRing % 2 == 0, "the LDS stage of step t is t % 2 = (t % kRing) % 2");
+  constexpr int KV = kBfBK / 8;              // 16-byte pieces per row of one k step
+  constexpr int BV = BN * KV * KS, BVT = (BV + NT - 1) / NT;
+  static_assert(RING >= 2 && RING % 2 == 0, "the LDS stage of stage t is t % 2 = (t % RING) % 2");
   static_assert(MODE == 0 || (TM * 16) % 32 == 0, "statistics partials are per 32-row block");
-  constexpr size_t kTileB = sizeof(uint16_t) * 2 * BN * kBfLd;
+  constexpr int kSub = BN * kBfLd;           // uint16 per k step of a stage
+  constexpr int kStage = KS * kSub;
+  constexpr size_t kTileB = sizeof(uint16_t) * 2 * kStage;
   constexpr size_t kBytesR = bf_red_bytes<BM, BN, MODE, DL>();
   constexpr size_t kBytes = kTileB > kBytesR ? kTileB : kBytesR;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  auto sB = reinterpret_cast<uint16_t (*)[BN][kBfLd]>(smem);
+  uint16_t *const sB = reinterpret_cast<uint16_t *>(smem);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -718,9 +719,10 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair 
   const int m0 = mt * BM, n0 = nt * BN;
   const int kbeg = MODE == 0 ? zc * kchunk : 0;
   const int kend = MODE == 0 ? min(K, kbeg + kchunk) : K;
-  const int nsteps = kend > kbeg ? (kend - kbeg) / kBfBK : 0;
+  const int nsub = kend > kbeg ? (kend - kbeg) / kBfBK : 0;   // k steps
+  const int nfull = nsub / KS, nst = (nsub + KS - 1) / KS;     // full and all stages
   const int g8 = 8 * (lane >> 4), r16 = lane & 15;
-  const int bcol = wn * TN * 16;
+  const int bread = (wn * TN * 16 + r16) * kBfLd + g8;   // this wave's B fragments in a k step
 
   f4v acc[TM][TN];
 #pragma unroll
@@ -728,70 +730,87 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair 
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = f4v{0.f, 0.f, 0.f, 0.f};
 
-  // this lane's piece of the first A fragment of the chunk, and per B element
-  // slot its row and k offset (slots past BV load element BV - 1 again and are
-  // not stored)
+  // this lane's piece of the first A fragment of the chunk; per B slot (slots
+  // past BV load slot BV - 1 again and are not stored) its global address at
+  // the chunk's first stage and its place in a stage
   const uint16_t *abase = A.hi + frag_off(m0 + wm * TM * 16, kbeg, A.ld) + (size_t)lane * 8;
   const size_t astep = (size_t)(A.ld >> 5) * 512;   // next 16-row tile
   const uint16_t *bbase[BVT];
+  int bput[BVT], bks[BVT];
 #pragma unroll
   for (int i = 0; i < BVT; ++i) {
     const int e = min(tid + i * NT, BV - 1);
-    bbase[i] = B.hi + (size_t)(n0 + e / KV) * B.ld + kbeg + (e % KV) * 8;
+    const int ks = e / (BN * KV), r = e % (BN * KV);
+    const int n = r / KV, c = r % KV;
+    bbase[i] = B.hi + (size_t)(n0 + n) * B.ld + kbeg + ks * kBfBK + c * 8;
+    bput[i] = ks * kSub + n * kBfLd + c * 8;
+    bks[i] = ks;
   }
-  u4v ah[kRing][TM], rb[kRing][BVT];
-  auto load_a = [&](int t, u4v (&dst)[TM]) {
-    const size_t ko = (size_t)min(t, nsteps - 1) * 512;
+  u4v ah[RING][KS][TM], rb[RING][BVT];
+  auto load_a = [&](int t, u4v (&dst)[KS][TM]) {
 #pragma unroll
-    for (int tm = 0; tm < TM; ++tm) dst[tm] = *reinterpret_cast<const u4v *>(abase + tm * astep + ko);
+    for (int ks = 0; ks < KS; ++ks) {
+      const size_t ko = (size_t)min(t * KS + ks, nsub - 1) * 512;
+#pragma unroll
+      for (int tm = 0; tm < TM; ++tm) dst[ks][tm] = *reinterpret_cast<const u4v *>(abase + tm * astep + ko);
+    }
   };
+  // B slot i belongs to k step bks[i] of a stage (bbase[i] includes its offset)
   auto load_b = [&](int t, u4v (&dst)[BVT]) {
-    const int ko = min(t, nsteps - 1) * kBfBK;
 #pragma unroll
-    for (int i = 0; i < BVT; ++i) dst[i] = *reinterpret_cast<const u4v *>(bbase[i] + ko);
+    for (int i = 0; i < BVT; ++i) {
+      const int ko = (min(t * KS + bks[i], nsub - 1) - bks[i]) * kBfBK;
+      dst[i] = *reinterpret_cast<const u4v *>(bbase[i] + ko);
+    }
   };
   auto store_b = [&](const u4v (&src)[BVT], int stage) {
 #pragma unroll
-    for (int i = 0; i < BVT; ++i) {
-      const int e = tid + i * NT;
-      if (BV % NT == 0 || e < BV) *reinterpret_cast<u4v *>(&sB[stage][e / KV][(e % KV) * 8]) = src[i];
-    }
+    for (int i = 0; i < BVT; ++i)
+      if (BV % NT == 0 || tid + i * NT < BV)
+        *reinterpret_cast<u4v *>(sB + stage * kStage + bput[i]) = src[i];
   };
-  auto mma = [&](const u4v (&a)[TM], int stage) {
+  // nk: k steps of the stage to multiply (KS, or fewer in a last partial stage)
+  auto mma = [&](const u4v (&a)[KS][TM], int stage, int nk) {
 #pragma unroll
-    for (int tn = 0; tn < TN; ++tn) {
-      const bf8v b = *reinterpret_cast<const bf8v *>(&sB[stage][bcol + tn * 16 + r16][g8]);
+    for (int ks = 0; ks < KS; ++ks) {
+      if (ks >= nk) break;
 #pragma unroll
-      for (int tm = 0; tm < TM; ++tm) acc[tm][tn] = mfma_bf(as_bf8(a[tm]), b, acc[tm][tn]);
+      for (int tn = 0; tn < TN; ++tn) {
+        const bf8v b = *reinterpret_cast<const bf8v *>(sB + stage * kStage + ks * kSub + bread +
+                                                       tn * 16 * kBfLd);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) acc[tm][tn] = mfma_bf(as_bf8(a[ks][tm]), b, acc[tm][tn]);
+      }
     }
   };
 
-  if (nsteps > 0) {
+  if (nsub > 0) {
 #pragma unroll
-    for (int p = 0; p < kRing; ++p) {
+    for (int p = 0; p < RING; ++p) {
       load_b(p, rb[p]);
       load_a(p, ah[p]);
     }
     store_b(rb[0], 0);
     __syncthreads();
     int t0 = 0;
-    for (; t0 + kRing <= nsteps; t0 += kRing) {
+    for (; t0 + RING <= nfull; t0 += RING) {
 #pragma unroll
-      for (int i = 0; i < kRing; ++i) {
+      for (int i = 0; i < RING; ++i) {
         const int t = t0 + i;
-        load_b(t + kRing, rb[i]);           // B of step t left rb[i] for LDS at step t - 1
-        mma(ah[i], i & 1);
-        load_a(t + kRing, ah[i]);
-        store_b(rb[(i + 1) % kRing], (i + 1) & 1);   // past the last step: never read
+        load_b(t + RING, rb[i]);            // B of stage t left rb[i] for LDS at stage t - 1
+        mma(ah[i], i & 1, KS);
+        load_a(t + RING, ah[i]);
+        store_b(rb[(i + 1) % RING], (i + 1) & 1);   // past the last stage: never read
         __syncthreads();
       }
     }
-    // the last nsteps % kRing steps: their operands are already loaded
+    // the last stages (fewer than RING full ones, then a partial one): their
+    // operands are already loaded
 #pragma unroll
-    for (int i = 0; i < kRing - 1; ++i) {
-      if (t0 + i < nsteps) {
-        mma(ah[i], i & 1);
-        store_b(rb[(i + 1) % kRing], (i + 1) & 1);
+    for (int i = 0; i < RING; ++i) {
+      if (t0 + i < nst) {
+        mma(ah[i], i & 1, min(KS, nsub - (t0 + i) * KS));
+        store_b(rb[(i + 1) % RING], (i + 1) & 1);
         __syncthreads();
       }
     }
@@ -808,6 +827,9 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair 
 // by 64, 112 and 96 columns, so that every launch width of a compacted run (a
 // multiple of 64, 96 or 224) has one, and 8 waves of 32 x 112 (split-K) or
 // 32 x 224 (point-row) that cover all 448 plan columns of a 441-plan batch.
+// Ring depth and k steps per stage (BF_DW's last two arguments) as measured
+// fastest on the large case: two stages of two k steps, four k steps in the
+// 64-column point-row tile, and four stages of one in the 448-column tiles.
 constexpr int kBfCfgCount = 10;
 struct BfCfg { int bm, bn; bool single_only; };
 static const BfCfg kBfCfgs[2][kBfCfgCount] = {
@@ -836,9 +858,9 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
 #define BF_DI(TMv, TNv, WMv)                                                                       \
   hipLaunchKernelGGL((k_gemm_bfd<TMv, TNv, WMv, 1, 1, TERMS, MODE, DL>), grid, dim3(64 * WMv), 0, s, A, B, \
                      K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
-#define BF_DW(TMv, TNv, WMv, WNv, OCCv)                                                            \
-  hipLaunchKernelGGL((k_gemm_b1<TMv, TNv, WMv, WNv, OCCv, MODE, DL>), grid, dim3(64 * WMv * WNv), 0, s, \
-                     A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
+#define BF_DW(TMv, TNv, WMv, WNv, OCCv, RINGv, KSv)                                                \
+  hipLaunchKernelGGL((k_gemm_b1<TMv, TNv, WMv, WNv, OCCv, RINGv, KSv, MODE, DL>), grid,                  \
+                     dim3(64 * WMv * WNv), 0, s, A, B, K, kchunk, mtiles, ntiles, P, ldp, pstride, ea)
   if constexpr (MODE == 0) {
     switch (cfg) {
       case 0: BF_ST(64, 32, 2, 1, 2); break;
@@ -848,16 +870,16 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(1, 6, 4); break;
       case 5: BF_DI(3, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_DW(3, 4, 4, 1, 3); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(3, 4, 4, 1, 3, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_DW(3, 7, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(3, 7, 4, 1, 2, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 8:
-        if constexpr (TERMS == 1) { BF_DW(3, 6, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(3, 6, 4, 1, 2, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 9:
-        if constexpr (TERMS == 1) { BF_DW(2, 7, 2, 4, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 7, 2, 4, 2, 4, 1); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
@@ -870,16 +892,16 @@ static hipError_t launch_bf(int cfg, int M, int N, int nchunk, hipStream_t s, Bf
       case 4: BF_DI(2, 6, 4); break;
       case 5: BF_DI(2, 4, 4); break;
       case 6:
-        if constexpr (TERMS == 1) { BF_DW(2, 4, 4, 1, 3); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 4, 4, 1, 3, 2, 4); } else { return hipErrorInvalidValue; }
         break;
       case 7:
-        if constexpr (TERMS == 1) { BF_DW(2, 7, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 7, 4, 1, 2, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 8:
-        if constexpr (TERMS == 1) { BF_DW(2, 6, 4, 1, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 6, 4, 1, 2, 2, 2); } else { return hipErrorInvalidValue; }
         break;
       case 9:
-        if constexpr (TERMS == 1) { BF_DW(2, 14, 4, 2, 2); } else { return hipErrorInvalidValue; }
+        if constexpr (TERMS == 1) { BF_DW(2, 14, 4, 2, 2, 4, 1); } else { return hipErrorInvalidValue; }
         break;
       default: return hipErrorInvalidValue;
     }
