@@ -65,6 +65,8 @@ TRAFFIC = {
             ("gemm_impl.h", "gemm_f32.hip", "kernels.h")),
     "bf16x3": (os.path.join(ROOT, "profiles", "gemm_c2_bf16_traffic.txt"),
                ("gemm_bf16.hip", "kernels.h")),
+    "bf16": (os.path.join(ROOT, "profiles", "gemm_c2_bf16r_traffic.txt"),
+             ("gemm_bf16.hip", "kernels.h")),
 }
 
 
