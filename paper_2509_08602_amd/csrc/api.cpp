@@ -318,6 +318,10 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   c->Smat = (double *)p;
   SETUP_RC(case_alloc(c, &p, (size_t)c->mAp * c->mAp * sizeof(double)));
   c->Sinv = (double *)p;
+  if (c->precision == LADMM_BF16) {
+    SETUP_RC(case_alloc(c, &p, (size_t)c->mAp * c->mAp * sizeof(float)));
+    c->Sinv32 = (float *)p;
+  }
 
   SETUP_HIP(hipMemcpyAsync(c->grp, hgrp.data(), c->Np * sizeof(int32_t), hipMemcpyHostToDevice, s));
   SETUP_HIP(hipMemcpyAsync(c->is_ld, hld.data(), (c->G + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -384,6 +388,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
     SETUP_RC(talloc((void **)&Pi, (size_t)nci * c->mAp * c->mAp * sizeof(double)));
     SETUP_HIP(gemm_tn<double>(s, X, c->mAp, X, c->mAp, Pi, c->mAp, c->mAp, c->mAp, c->mAp, nci, nullptr));
     SETUP_HIP(reduce_partials<double>(s, Pi, (size_t)c->mAp * c->mAp, nci, c->mAp, c->mAp, c->mAp, c->Sinv, c->mAp));
+    if (c->Sinv32 != nullptr) SETUP_HIP(to_f32(s, c->Sinv, c->Sinv32, (size_t)c->mAp * c->mAp));
   }
   int hinfo = 0;
   SETUP_HIP(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -645,6 +650,12 @@ int create_batch_impl(ladmm_case *c, int32_t k, const ladmm_weights *w, const ui
     B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * sizeof(double))); b->gref = (double *)p;
     B_RC(batch_alloc(b, &p, (size_t)c->ntp * kp * sizeof(double))); b->vref = (double *)p;
     B_RC(batch_alloc(b, &p, (size_t)kp * c->Np * sizeof(uint16_t))); b->dW = (uint16_t *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->rref = (double *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(double))); b->vfull = (double *)p;
+    B_RC(batch_alloc(b, &p, (size_t)c->mAp * kp * sizeof(float))); b->r32 = (float *)p;
+    B_HIP(hipMemsetAsync(b->rref, 0, (size_t)c->mAp * kp * sizeof(double), b->stream));
+    B_HIP(hipMemsetAsync(b->vfull, 0, (size_t)c->mAp * kp * sizeof(double), b->stream));
+    B_HIP(hipMemsetAsync(b->r32, 0, (size_t)c->mAp * kp * sizeof(float), b->stream));
     B_HIP(hipMemsetAsync(b->xref, 0, (size_t)c->Np * kp * sizeof(float), b->stream));
     B_HIP(hipMemsetAsync(b->wref, 0, (size_t)c->Np * kp * sizeof(float), b->stream));
     B_HIP(hipMemsetAsync(b->gref, 0, (size_t)c->ntp * kp * sizeof(double), b->stream));
@@ -875,16 +886,25 @@ int iterate_bfr(ladmm_batch *b, int phase) {
     PROF(9, (gemm_bf_tn(s, DT, W, (float *)b->P1, kp, c->ntp, kw, c->Np, c->nchunk1, 3, b->cfg1r)));
   else
     PROF(0, (gemm_bf_tn(s, DT, dW, (float *)b->P1, kp, c->ntp, kw, c->Np, c->nchunk1, 1, b->cfg1)));
+  // S^-1 r refined like the dose products: the refresh multiplies r by the FP64
+  // inverse and records (r, v) for the running plans; a hot iteration adds the
+  // FP32 product of the FP32 inverse with r - r_ref to that v (S^-1 is linear,
+  // so any recorded pair gives S^-1 r; FP32 rounds only the change)
   PROF(1, (rhs<float>(s, sa, (const float *)b->P1, (size_t)c->ntp * kp, c->nchunk1, b->qs, b->q2, b->r,
-                      refresh ? nullptr : b->gref, refresh ? b->gref : nullptr)));
-  PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kw, c->mAp,
-                           c->nchunk2, nullptr, b->cfg_s)));
-  if (refresh)
+                      refresh ? nullptr : b->gref, refresh ? b->gref : nullptr,
+                      refresh ? b->rref : nullptr, refresh ? nullptr : b->rref,
+                      refresh ? nullptr : b->r32)));
+  if (refresh) {
+    PROF(2, (gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, kw, c->mAp,
+                             c->nchunk2, nullptr, b->cfg_s)));
     PROF(3, (vreduce_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, (uint16_t *)V.hi,
-                        (uint16_t *)V.lo, b->vref)));
-  else
-    PROF(3, (vreduce_delta_bf(s, sa, b->P2, (size_t)c->mAp * kp, c->nchunk2, b->v, b->vref,
-                              (uint16_t *)V.hi)));
+                        (uint16_t *)V.lo, b->vref, b->vfull)));
+  } else {
+    PROF(2, (gemm_tn<float>(s, c->Sinv32, c->mAp, b->r32, kp, (float *)b->P2, kp, c->mAp, kw, c->mAp,
+                            c->nchunk2, nullptr, b->cfg_s)));
+    PROF(3, (vreduce_delta_bf(s, sa, (const float *)b->P2, (size_t)c->mAp * kp, c->nchunk2, b->vfull,
+                              b->v, b->vref, (uint16_t *)V.hi)));
+  }
   PROF(3, (post(s, sa, b->v, b->qs, b->q2, refresh ? b->post_stats : nullptr, &b->post_blocks)));
   EpiArgs<float> ea{};
   ea.q = (float *)b->q;
@@ -1055,14 +1075,18 @@ int autotune(ladmm_batch *b) {
   }
   hipFree(noact);
   if (e != hipSuccess) return fail(LADMM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
-  // the FP64 S^-1 r product (it writes only its split partials)
+  // the S^-1 r product (it writes only its split partials; LADMM_BF16 tunes its
+  // hot iterations' FP32 product, the FP64 one runs once per chunk)
   float best_s = 1e30f;
   for (int cfg = 0; cfg < kGemmCfgs && e == hipSuccess; ++cfg) {
     if (!gemm_tn_cfg_ok(cfg, c->mAp, b->kact)) continue;
     float tot = 0.f;
     for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
       e = hipEventRecord(b->ev0, s);
-      if (e == hipSuccess)
+      if (e == hipSuccess && c->Sinv32 != nullptr)
+        e = gemm_tn<float>(s, c->Sinv32, c->mAp, b->r32, kp, (float *)b->P2, kp, c->mAp, b->kact,
+                           c->mAp, c->nchunk2, nullptr, cfg);
+      else if (e == hipSuccess)
         e = gemm_tn<double>(s, c->Sinv, c->mAp, b->r, kp, b->P2, kp, c->mAp, b->kact, c->mAp,
                             c->nchunk2, nullptr, cfg);
       if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
@@ -1267,6 +1291,8 @@ int permute_columns(ladmm_batch *b, const std::vector<int> &src_k) {
     arrs.push_back({b->wref, (size_t)c->Np, 4, false});
     arrs.push_back({b->gref, (size_t)c->ntp, 8, false});
     arrs.push_back({b->vref, (size_t)c->ntp, 8, false});
+    arrs.push_back({b->rref, (size_t)c->mAp, 8, false});
+    arrs.push_back({b->vfull, (size_t)c->mAp, 8, false});
     arrs.push_back({b->dW, (size_t)c->Np, 2, true});
   }
   if (b->mask) arrs.push_back({b->mask, (size_t)b->mask_words, 8, true});

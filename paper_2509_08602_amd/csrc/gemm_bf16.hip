@@ -1014,7 +1014,8 @@ hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int
 // with vref (a refresh of LADMM_BF16) the value the pairs carry.
 __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,
                              double *__restrict__ v, uint16_t *__restrict__ vh,
-                             uint16_t *__restrict__ vl, double *__restrict__ vref) {
+                             uint16_t *__restrict__ vl, double *__restrict__ vref,
+                             double *__restrict__ vout) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const int m = blockIdx.x * 4 + threadIdx.y;
   if (m >= a.L.mAp || j >= a.kp) return;
@@ -1023,6 +1024,7 @@ __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t 
 #pragma unroll 8
   for (int z = 0; z < nchunk; ++z) acc += P2[z * zstride + idx];
   v[idx] = acc;
+  if (vout != nullptr && a.active[j]) vout[idx] = acc;
   if (m < a.L.ntp) {
     uint16_t h, l;
     split_pair(acc, h, l);
@@ -1033,31 +1035,35 @@ __global__ void k_vreduce_bf(SmallArgs a, const double *__restrict__ P2, size_t 
 }
 
 hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                      double *v, uint16_t *vh, uint16_t *vl, double *vref) {
+                      double *v, uint16_t *vh, uint16_t *vl, double *vref, double *vout) {
   hipLaunchKernelGGL(k_vreduce_bf, dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s, a,
-                     P2, zstride, nchunk, v, vh, vl, vref);
+                     P2, zstride, nchunk, v, vh, vl, vref, vout);
   return hipGetLastError();
 }
 
-// v = sum of the S^-1 r partials; dv = bf16(v_top - vref) plan-major (kp x ntp).
-__global__ void k_vreduce_delta_bf(SmallArgs a, const double *__restrict__ P2, size_t zstride,
-                                   int nchunk, double *__restrict__ v,
-                                   const double *__restrict__ vref, uint16_t *__restrict__ dv) {
+// v = vbase + the sum of the FP32 partials of S^-1 (r - r_ref); dv = bf16(v_top -
+// vref) plan-major (kp x ntp).
+__global__ void k_vreduce_delta_bf(SmallArgs a, const float *__restrict__ P2, size_t zstride,
+                                   int nchunk, const double *__restrict__ vbase,
+                                   double *__restrict__ v, const double *__restrict__ vref,
+                                   uint16_t *__restrict__ dv) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const int m = blockIdx.x * 4 + threadIdx.y;
   if (m >= a.L.mAp || j >= a.kp) return;
   const size_t idx = (size_t)m * a.kp + j;
   double acc = 0.0;
 #pragma unroll 8
-  for (int z = 0; z < nchunk; ++z) acc += P2[z * zstride + idx];
+  for (int z = 0; z < nchunk; ++z) acc += (double)P2[z * zstride + idx];
+  acc += vbase[idx];
   v[idx] = acc;
   if (m < a.L.ntp) dv[(size_t)j * a.L.ntp + m] = bf_round((float)(acc - vref[idx]));
 }
 
-hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride,
-                            int nchunk, double *v, const double *vref, uint16_t *dv) {
+hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const float *P2, size_t zstride,
+                            int nchunk, const double *vbase, double *v, const double *vref,
+                            uint16_t *dv) {
   hipLaunchKernelGGL(k_vreduce_delta_bf, dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0,
-                     s, a, P2, zstride, nchunk, v, vref, dv);
+                     s, a, P2, zstride, nchunk, vbase, v, vref, dv);
   return hipGetLastError();
 }
 

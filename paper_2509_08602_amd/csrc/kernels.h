@@ -109,11 +109,16 @@ struct SmallArgs {
 // dose-point part G = sum of the partials; with gref (the BF16 refinement's hot
 // iterations) G = gref + partials (the product of the change since the last
 // refresh), and with gout (its refresh) G is also stored there for the
-// running plans.
+// running plans.  The refinement of S^-1 r: with rout (a refresh) r is also
+// stored there for the running plans; with r32 (a hot iteration) r32 = r - rsub
+// in FP32.
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
                const double *qs, const double *q2, double *r, const double *gref = nullptr,
-               double *gout = nullptr);
+               double *gout = nullptr, double *rout = nullptr, const double *rsub = nullptr,
+               float *r32 = nullptr);
+// y = (float) x, n values.
+hipError_t to_f32(hipStream_t s, const double *x, float *y, size_t n);
 // v = sum of the Sinv r partials (mAp x kp) and vT = (T) v_top (ntp x kp).
 template <typename T>
 hipError_t vreduce(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
@@ -232,12 +237,16 @@ hipError_t split_dose_bf16(hipStream_t s, const double *Dt, const double *E, int
                            uint16_t *Dh, uint16_t *Dl, uint16_t *DTh, uint16_t *DTl);
 // v_top and the scaled shot times as plan-major pairs (kp x ntp) for the products.
 // With vref != NULL (a refresh): also vref := hi + lo (the value the pairs
-// carry) for the running plans.
+// carry) for the running plans, and with vout, v itself (all mAp rows).
 hipError_t vreduce_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride, int nchunk,
-                      double *v, uint16_t *vh, uint16_t *vl, double *vref = nullptr);
-// v and dv = bf16(v_top - vref) plan-major (kp x ntp): the hot iterations of LADMM_BF16.
-hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const double *P2, size_t zstride,
-                            int nchunk, double *v, const double *vref, uint16_t *dv);
+                      double *v, uint16_t *vh, uint16_t *vl, double *vref = nullptr,
+                      double *vout = nullptr);
+// The hot iterations of LADMM_BF16: v = vbase + the FP32 partials of
+// S^-1 (r - r_ref) (summed in FP64), and dv = bf16(v_top - vref) plan-major
+// (kp x ntp).
+hipError_t vreduce_delta_bf(hipStream_t s, const SmallArgs &a, const float *P2, size_t zstride,
+                            int nchunk, const double *vbase, double *v, const double *vref,
+                            uint16_t *dv);
 hipError_t shot_scaled_bf(hipStream_t s, const SmallArgs &a, const double *q2, uint16_t *th,
                           uint16_t *tl);
 // z1 = clip(q, 0, u) as plan-major pairs (kp x Np), the certificate's operand.

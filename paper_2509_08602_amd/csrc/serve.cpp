@@ -237,6 +237,8 @@ int upload(Lane &L) {
         HIPC(zero_columns<float>(s, b->wref, c->Np, kp, L.d_reset));
         HIPC(zero_columns<double>(s, b->gref, c->ntp, kp, L.d_reset));
         HIPC(zero_columns<double>(s, b->vref, c->ntp, kp, L.d_reset));
+        HIPC(zero_columns<double>(s, b->rref, c->mAp, kp, L.d_reset));
+        HIPC(zero_columns<double>(s, b->vfull, c->mAp, kp, L.d_reset));
         HIPC(zero_plan_rows_bf(s, b->dW, kp, c->Np, L.d_reset, 1));
       }
     }

@@ -328,7 +328,8 @@ template <typename T>
 __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int nchunk,
                       const double *__restrict__ qs, const double *__restrict__ q2,
                       double *__restrict__ r, const double *__restrict__ gref,
-                      double *__restrict__ gout) {
+                      double *__restrict__ gout, double *__restrict__ rout,
+                      const double *__restrict__ rsub, float *__restrict__ r32) {
   const int j = blockIdx.y * 64 + threadIdx.x;
   const int m = blockIdx.x * 4 + threadIdx.y;
   const SmallLayout &L = a.L;
@@ -359,18 +360,32 @@ __global__ void k_rhs(SmallArgs a, const T *__restrict__ P1, size_t zstride, int
     const double w2 = 2.0 * fmin(q2v, a.bbot[(size_t)i * kp + j]) - q2v;
     out = a.beta * a.E[m] * sum - w2;
   }
-  r[(size_t)m * kp + j] = out;
+  const size_t idx = (size_t)m * kp + j;
+  r[idx] = out;
+  if (rout != nullptr && a.active[j]) rout[idx] = out;
+  if (r32 != nullptr) r32[idx] = (float)(out - rsub[idx]);
 }
 
 template <typename T>
 hipError_t rhs(hipStream_t s, const SmallArgs &a, const T *P1, size_t zstride, int nchunk,
-               const double *qs, const double *q2, double *r, const double *gref, double *gout) {
+               const double *qs, const double *q2, double *r, const double *gref, double *gout,
+               double *rout, const double *rsub, float *r32) {
   hipLaunchKernelGGL((k_rhs<T>), dim3((a.L.mAp + 3) / 4, (a.kp + 63) / 64), dim3(64, 4), 0, s, a, P1,
-                     zstride, nchunk, qs, q2, r, gref, gout);
+                     zstride, nchunk, qs, q2, r, gref, gout, rout, rsub, r32);
   return hipGetLastError();
 }
-template hipError_t rhs<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, const double *, const double *, double *, const double *, double *);
-template hipError_t rhs<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, const double *, const double *, double *, const double *, double *);
+template hipError_t rhs<float>(hipStream_t, const SmallArgs &, const float *, size_t, int, const double *, const double *, double *, const double *, double *, double *, const double *, float *);
+template hipError_t rhs<double>(hipStream_t, const SmallArgs &, const double *, size_t, int, const double *, const double *, double *, const double *, double *, double *, const double *, float *);
+
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+hipError_t to_f32(hipStream_t s, const double *x, float *y, size_t n) {
+  hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
 
 template <typename T>
 __global__ void k_vreduce(SmallArgs a, const double *__restrict__ P2, size_t zstride, int nchunk,

@@ -95,6 +95,7 @@ struct ladmm_case {
   double *gvec = nullptr;    // ntp
   double *Smat = nullptr;    // mAp x mAp
   double *Sinv = nullptr;    // mAp x mAp
+  float *Sinv32 = nullptr;   // LADMM_BF16: Sinv in FP32 for the hot iterations
   std::vector<ladmm_group> groups;
   std::vector<int32_t> hgrp;
   std::vector<int64_t> counts;
@@ -140,6 +141,10 @@ struct ladmm_batch {
   // LADMM_BF16 (refinement): references of the last refresh and the change of
   // W since it (plan-major, kp x Np)
   float *xref = nullptr, *wref = nullptr;   // Np x kp
+  // and of S^-1 r: r and v of the last refresh (mAp x kp), and the change of r
+  // since it in FP32
+  double *rref = nullptr, *vfull = nullptr;
+  float *r32 = nullptr;
   double *gref = nullptr, *vref = nullptr;  // ntp x kp
   uint16_t *dW = nullptr;
   // certificate of a check: z1 of the dose points (point-major T, or plan-major
