@@ -299,7 +299,10 @@ int ladmm_batch_set_compaction(ladmm_batch *b, int32_t on);
 int ladmm_batch_set_profiling(ladmm_batch *b, int32_t on);
 int ladmm_batch_kernel_times(const ladmm_batch *b, double *ms_total, int64_t *launches);
 
-/* One call: create a batch, run it to convergence, write results, destroy it. */
+/* One call for the stacked plans of Sec. 2.B: create a batch, run the ADMM
+ * iterations of Eq. (admm) to each plan's stopping rule (ladmm_batch_run),
+ * write the results as ladmm_batch_results does, destroy the batch.  Errors as
+ * ladmm_batch_create, ladmm_batch_run and ladmm_batch_results. */
 int ladmm_solve_batch(ladmm_case *c, int32_t k, const ladmm_weights *w,
                       const uint64_t *ld_mask, const ladmm_opts *opts, ladmm_result *out);
 

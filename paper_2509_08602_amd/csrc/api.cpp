@@ -21,8 +21,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "state.h"
@@ -198,12 +200,7 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
       return fail(LADMM_E_INVALID, "point " + std::to_string(p) + ": group out of range");
     counts[g]++;
   }
-  const size_t nd = (size_t)d->n_points * n_t;
-  for (size_t e = 0; e < nd; ++e) {
-    const double v = d->dose[e];
-    if (!(v >= 0.0) || !std::isfinite(v))
-      return fail(LADMM_E_INVALID, "dose entry " + std::to_string(e) + " is negative or not finite");
-  }
+  const size_t nd = (size_t)d->n_points * n_t;   // dose entries: checked on the device
 
   ladmm_case *c = new ladmm_case();
   c->ctx = ctx;
@@ -340,6 +337,17 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   SETUP_RC(talloc((void **)&dinv, c->Np * sizeof(double)));
   SETUP_RC(talloc((void **)&Dt, (size_t)c->Np * c->ntp * sizeof(double)));
   SETUP_HIP(hipMemcpyAsync(dphi, d->dose, nd * sizeof(double), hipMemcpyHostToDevice, s));
+  // every dose entry >= 0 and finite, checked where the entries now are
+  unsigned long long *dbad = nullptr, hbad = ~0ull;
+  SETUP_RC(talloc((void **)&dbad, sizeof(unsigned long long)));
+  SETUP_HIP(hipMemcpyAsync(dbad, &hbad, sizeof(hbad), hipMemcpyHostToDevice, s));
+  SETUP_HIP(check_dose(s, dphi, nd, dbad));
+  SETUP_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(hbad), hipMemcpyDeviceToHost, s));
+  SETUP_HIP(hipStreamSynchronize(s));
+  if (hbad != ~0ull) {
+    fail(LADMM_E_INVALID, "dose entry " + std::to_string(hbad) + " is negative or not finite");
+    return tclean(LADMM_E_INVALID);
+  }
   SETUP_HIP(hipMemcpyAsync(dsig64, hsig.data(), c->Np * sizeof(double), hipMemcpyHostToDevice, s));
   SETUP_HIP(hipMemcpyAsync(dinv, hinv.data(), c->Np * sizeof(double), hipMemcpyHostToDevice, s));
   SETUP_HIP(scale_dose(s, dphi, c->N, n_t, dsig64, dinv, Dt, c->Np, c->ntp));
@@ -2118,11 +2126,21 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
       rc = fail(LADMM_E_INVALID, "passes: empty or too large pass");
       break;
     }
-    std::vector<double> dose2((size_t)N2 * n_t);
+    // every row is written below, so the buffer is not cleared first; the kept
+    // rows (7 GB at 180,000 x 4,800) are copied by several host threads
+    std::unique_ptr<double[]> dose2(new double[(size_t)N2 * n_t]);
     std::vector<int32_t> grp2(N2);
-    for (size_t i = 0; i < keep.size(); ++i) {
-      std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
-      grp2[i] = d1->point_group[keep[i]];
+    {
+      const size_t nk = keep.size();
+      const size_t nth = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+      std::vector<std::thread> pool;
+      for (size_t t = 0; t < nth; ++t)
+        pool.emplace_back([&, t] {
+          for (size_t i = nk * t / nth; i < nk * (t + 1) / nth; ++i)
+            std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
+        });
+      for (std::thread &th : pool) th.join();
+      for (size_t i = 0; i < nk; ++i) grp2[i] = d1->point_group[keep[i]];
     }
     const int W2 = (int)((N2 + 63) / 64);
     std::vector<uint64_t> mask2((size_t)k * W2, 0);
@@ -2145,7 +2163,7 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
     }
     ladmm_case_desc d2 = *d1;
     d2.n_points = (int32_t)N2;
-    d2.dose = dose2.data();
+    d2.dose = dose2.get();
     d2.point_group = grp2.data();
     rc = ladmm_create_case(ctx, &d2, &cur_c);
     if (rc) break;

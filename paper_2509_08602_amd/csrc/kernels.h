@@ -75,6 +75,9 @@ hipError_t gemm_nn(hipStream_t s, int epi, const T *A, int lda, const T *B, int 
 
 // ---- setup ------------------------------------------------------------------
 // Dt[p][t] = sig[p] * phi[p][t] / thr[p]; zero padding rows/cols (FP64).
+// The smallest index of a negative or non-finite dose entry into *first (set
+// to UINT64_MAX by the caller).
+hipError_t check_dose(hipStream_t s, const double *phi, size_t n, unsigned long long *first);
 hipError_t scale_dose(hipStream_t s, const double *phi, int N, int n_t, const double *sig,
                       const double *inv_thr, double *Dt, int Np, int ntp);
 // out[p][t] = (T)(Dt[p][t] * E[t])

@@ -34,6 +34,20 @@ __global__ void k_scale_dose(const double *__restrict__ phi, int N, int n_t,
   }
 }
 
+// The smallest index of a dose entry that is negative or not finite, into
+// *first (which the caller sets to UINT64_MAX); unchanged if there is none.
+__global__ void k_check_dose(const double *__restrict__ phi, size_t n, unsigned long long *first) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const double v = phi[e];
+    if (!(v >= 0.0) || !isfinite(v)) atomicMin(first, (unsigned long long)e);
+  }
+}
+
+hipError_t check_dose(hipStream_t s, const double *phi, size_t n, unsigned long long *first) {
+  hipLaunchKernelGGL(k_check_dose, dim3(4096), dim3(256), 0, s, phi, n, first);
+  return hipGetLastError();
+}
+
 hipError_t scale_dose(hipStream_t s, const double *phi, int N, int n_t, const double *sig,
                       const double *inv_thr, double *Dt, int Np, int ntp) {
   hipLaunchKernelGGL(k_scale_dose, dim3(4096), dim3(256), 0, s, phi, N, n_t, sig, inv_thr, Dt,

@@ -154,6 +154,11 @@ inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v)
   *p += v;
   return o;
 }
+inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v) {
+  unsigned long long o = *p;
+  if (v < o) *p = v;
+  return o;
+}
 
 // ---- runtime API ------------------------------------------------------------
 typedef int hipError_t;

@@ -265,9 +265,17 @@ def test_errors_are_reported(ctx, c0):
     bad = c0.dose.copy()
     bad[3, 5] = -1.0
     groups = [(g.type, g.structure, g.threshold, g.share) for g in c0.groups]
+    used = ctx.used_bytes
     with pytest.raises(ladmm.LadmmError) as e:
         ladmm.Case(ctx, bad, c0.group, groups, c0.n_iso)
     assert e.value.code == ladmm.E_INVALID
+    # checked on the device: the first bad entry is named, nothing stays allocated
+    assert f"dose entry {3 * c0.n_t + 5} " in str(e.value), str(e.value)
+    assert ctx.used_bytes == used
+    bad[7, 1] = np.nan
+    with pytest.raises(ladmm.LadmmError) as e:
+        ladmm.Case(ctx, bad, c0.group, groups, c0.n_iso)
+    assert f"dose entry {3 * c0.n_t + 5} " in str(e.value), str(e.value)
     dc = ladmm.Case.from_case(ctx, c0, "f64")
     w = cases.config_weights(0).copy()
     w[2, 3] = 0.0
