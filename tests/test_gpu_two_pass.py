@@ -64,6 +64,45 @@ def test_two_pass_c0_matches_oracle():
     assert np.all(rel < 1e-3), rel
 
 
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_two_pass_c0_reduced_precision_matches_oracle(precision):
+    """Both passes in FP32 and in the BF16 refinement precision: the second-pass
+    point set is the oracle's band + Algorithm 1 from the same pass-1 shot times
+    (bit-exact), and every pass-2 plan, stopped on its certified gap, is within
+    1e-3 of the exact optimum of the rebuilt LP."""
+    say("two-pass c0", precision)
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    k = w.shape[0]
+    ld_group = [g.type for g in case.groups].index(cases.LD)
+    cand = case.ld_candidates
+    phi = case.kernel.dose_rate(cand)
+    d_ld, delta = 0.5 * case.prescription_mean, 0.1 * case.prescription_mean
+    n_ld = np.full(k, 500)
+    opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
+                         tol_dual=1e-4, tol_cert=9e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+    ctx = ladmm.Context(0)
+    r1, r2, P, n2, times = ladmm.two_pass(ctx, case, w, phi, d_ld, delta, n_ld, 12345, ld_group,
+                                          precision, opts)
+    vols = odose.ld_band(odose.dose(phi, r1["t"].T), d_ld, delta)
+    Pref, pref = oalg1.select_ld_points(vols, n_ld, 12345)
+    assert P.tolist() == Pref
+    keep = np.nonzero(case.group != ld_group)[0]
+    case2 = case.with_points(keep, extra_ld=cand[np.array(Pref)], ld_group=ld_group)
+    assert case2.n_points == n2
+    mask2 = np.zeros((k, n2), bool)
+    mask2[:, len(keep):] = oalg1.masks_over(Pref, pref)
+    lp2 = olp.assemble(case2, w, mask2)
+    Fstar = np.array([-solve_plan(lp2, j).objective for j in range(k)])
+    F2 = olp.planning_objective(case2, w, r2["t"].T, mask2)[0]
+    # the device's F(t) of its own shot times, in the iteration precision
+    assert np.max(np.abs(F2 - r2["objective"]) / Fstar) < 1e-4
+    rel = np.abs(F2 - Fstar) / Fstar
+    say("pass-2 rel err", rel, "status", r2["plan_status"], "iters", r2["iters"])
+    assert np.all(r2["plan_status"] == ladmm.PLAN_CONVERGED), r2["plan_status"]
+    assert np.all(rel < 1e-3), rel
+
+
 def test_two_pass_two_low_dose_thresholds_c0():
     """Two low-dose groups (thresholds 0.5 and 0.25 of the prescription, App. A)
     replaced in one call: each set's point set is the oracle's band + Algorithm 1
