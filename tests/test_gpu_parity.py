@@ -319,6 +319,31 @@ def test_iteration_parity_c1(ctx, c1, precision):
         assert err < 2e-3, f"{name} rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-3), ("bf16x3", 2e-3), ("bf16", 3e-2)])
+def test_iteration_parity_441_plans(ctx, c0, precision, tol):
+    """All 441 plans of the 21 x 21 slider grid (448 launched columns, the
+    autotuned tiles of that width) on the small case: 3 iterations element by
+    element against the FP64 oracle.  FP32 and the BF16 pairs round as in the
+    81-plan test; the refinement precision's first products (zero references:
+    single BF16 products of the full operands until the chunk's refresh) carry
+    BF16 rounding, 2^-9 relative per operand, hence 3e-2."""
+    say("iteration parity c0, 441 plans", precision)
+    w = cases.config_weights(2)
+    assert w.shape[0] == 441
+    _, slp, rho = oracle_setup(c0, w)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(rho0=1000.0, w0_bot=cases.W0_BOT, adapt_rho=False))
+    b.iterate(3)
+    say("  tiles", b.tiles())
+    st = oadmm.admm_iterate(slp, rho, 3)
+    z1, y1, z2, y2 = b.export()
+    b.close()
+    for name, got, ref in (("z1", z1, st.z1), ("y1", y1, st.y1), ("z2", z2, st.z2),
+                           ("y2", y2, st.y2)):
+        err = rel_err(got, ref)
+        assert err < tol, f"{name} rel err {err:.3e}"
+
+
 @pytest.mark.parametrize("precision", ["f32", "bf16x3", "bf16"])
 def test_solve_c1_sampled_exact(ctx, c1, precision):
     """Solve of all 81 plans; sampled plans against their exact optimum."""
