@@ -319,6 +319,37 @@ def test_iteration_parity_c1(ctx, c1, precision):
         assert err < 2e-3, f"{name} rel err {err:.3e}"
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 2e-3)])
+def test_check_statistics_match_oracle(ctx, c0, precision, tol):
+    """The per-plan statistics of a check (the primal and dual residuals, c'z1,
+    F(t) and the relative gap) against the oracle's own computation of them,
+    from the same state one iteration earlier: the device's stopping decisions
+    rest on these numbers."""
+    say("check statistics c0", precision)
+    w = cases.config_weights(0)
+    lp, slp, rho = oracle_setup(c0, w)
+    dc = ladmm.Case.from_case(ctx, c0, precision)
+    b = ladmm.Batch(dc, w, opts=ladmm.Options(check_every=50, tol_gap=0.0, rho0=1000.0,
+                                              w0_bot=cases.W0_BOT, adapt_rho=False))
+    b.iterate(49)
+    prev = oadmm.ADMMState(*b.export())
+    b.iterate(1)                      # a chunk of one iteration ends with a check
+    res = b.results()
+    b.close()
+    nxt = oadmm.admm_iterate(slp, rho, 1, prev)
+    r_pri, r_dual = oadmm.residuals(slp, rho, nxt)
+    cz = oadmm.dual_objective(slp, nxt)
+    t = oadmm.shot_times(slp, rho, nxt)[0]
+    F = olp.planning_objective(c0, w, t)[0]
+    gap = np.abs(F + cz) / F
+    say("  r_pri", float(r_pri.max()), "r_dual", float(r_dual.max()), "gap", float(gap.max()))
+    assert np.max(np.abs(res["r_pri"] - r_pri) / r_pri) < tol
+    assert np.max(np.abs(res["r_dual"] - r_dual) / r_dual) < tol
+    assert np.max(np.abs(res["dual_obj"] - cz) / np.abs(F)) < tol
+    assert np.max(np.abs(res["objective"] - F) / F) < tol
+    assert np.max(np.abs(res["rel_gap"] - gap)) < tol
+
+
 @pytest.mark.parametrize("precision,tol", [("f32", 2e-3), ("bf16x3", 2e-3), ("bf16", 3e-2)])
 def test_iteration_parity_441_plans(ctx, c0, precision, tol):
     """All 441 plans of the 21 x 21 slider grid (448 launched columns, the
