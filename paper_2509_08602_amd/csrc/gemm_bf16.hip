@@ -687,13 +687,13 @@ __global__ __launch_bounds__(64 * WM * WN, bf_min_waves(TM, TN)) void k_gemm_bfd
 // (addresses past the last k step are clamped to it and the data is never
 // used), so that the compiler's waits name exact counts and about RING - 1
 // stages of loads stay in flight.  The last stage may hold fewer than KS k
-// steps; its MFMAs past the end are skipped.  Per stage: the B load of stage t + RING goes
-// out first, then the MFMAs of stage t, then the A load of stage t + RING into
-// the slot just used, and the LDS store of B for stage t + 1.  The waves form a
-// WM x WN grid (a workgroup spans up to all plan columns).  Every accumulator
-// takes one MFMA per k step in k order, as in the other kernels, so the results
-// are the same bits.  OCC: waves per SIMD the registers must allow.
-// (kend - kbeg) % 32 == 0.
+// steps; its MFMAs past the end are skipped.  Per stage: the B load of stage
+// t + RING goes out first, then the MFMAs of stage t, then the A load of stage
+// t + RING into the slot just used, and the LDS store of B for stage t + 1.
+// The waves form a WM x WN grid (a workgroup spans up to all plan columns).
+// Every accumulator takes one MFMA per k step in k order, as in the other
+// kernels, so the results are the same bits.  OCC: waves per SIMD the
+// registers must allow.  (kend - kbeg) % 32 == 0.
 template <int TM, int TN, int WM, int WN, int OCC, int RING, int KS, int MODE, int DL>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void k_gemm_b1(BfPair A, BfPair B, int K, int kchunk,
                                                                int mtiles, int ntiles,
