@@ -21,10 +21,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <memory>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "state.h"
@@ -173,11 +171,15 @@ int balanced_chunks(int K, int tiles, int min_rows, int rounds_min) {
   return best;
 }
 
-int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out) {
+// dose_dev: the N x n_t dose rates already on the device (caller-owned; d->dose
+// is then not read).  keep_dose: receives the device copy of the dose rates
+// made from d->dose, which the caller then owns (hipFree), for later passes.
+int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out,
+                     const double *dose_dev = nullptr, double **keep_dose = nullptr) {
   if (!ctx || !d || !out) return fail(LADMM_E_INVALID, "null argument");
   if (d->n_points < 1 || d->n_iso < 1 || d->n_sectors < 1 || d->n_collimators < 1)
     return fail(LADMM_E_INVALID, "sizes must be positive");
-  if (!d->dose || !d->point_group || !d->groups || d->n_groups < 1)
+  if ((!d->dose && !dose_dev) || !d->point_group || !d->groups || d->n_groups < 1)
     return fail(LADMM_E_INVALID, "dose, point_group and groups are required");
   if (!(d->prescription_mean > 0) || !(d->phi_cal > 0))
     return fail(LADMM_E_INVALID, "prescription_mean and phi_cal must be > 0");
@@ -332,11 +334,15 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
   }
 
   // dose matrix -> D~ = sign * phi / D_alpha (FP64, padded)
-  SETUP_RC(talloc((void **)&dphi, nd * sizeof(double)));
+  if (dose_dev != nullptr) {
+    dphi = const_cast<double *>(dose_dev);   // read only
+  } else {
+    SETUP_RC(talloc((void **)&dphi, nd * sizeof(double)));
+    SETUP_HIP(hipMemcpyAsync(dphi, d->dose, nd * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   SETUP_RC(talloc((void **)&dsig64, c->Np * sizeof(double)));
   SETUP_RC(talloc((void **)&dinv, c->Np * sizeof(double)));
   SETUP_RC(talloc((void **)&Dt, (size_t)c->Np * c->ntp * sizeof(double)));
-  SETUP_HIP(hipMemcpyAsync(dphi, d->dose, nd * sizeof(double), hipMemcpyHostToDevice, s));
   // every dose entry >= 0 and finite, checked where the entries now are
   unsigned long long *dbad = nullptr, hbad = ~0ull;
   SETUP_RC(talloc((void **)&dbad, sizeof(unsigned long long)));
@@ -416,6 +422,13 @@ int create_case_impl(ladmm_ctx *ctx, const ladmm_case_desc *d, ladmm_case **out)
     return tclean(LADMM_E_NUMERIC);
   }
   SETUP_HIP(hipEventElapsedTime(&c->setup_ms, e0, e1));
+  if (keep_dose != nullptr) {
+    *keep_dose = nullptr;
+    if (dose_dev == nullptr) {   // hand the device copy of the dose rates to the caller
+      temps.erase(std::find(temps.begin(), temps.end(), (void *)dphi));
+      *keep_dose = dphi;
+    }
+  }
   for (void *t : temps) hipFree(t);
   hipStreamDestroy(s);
   hipEventDestroy(e0);
@@ -2085,8 +2098,29 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
   auto t0 = clk::now();
   ladmm_case *cur_c = nullptr;
   ladmm_batch *cur_b = nullptr;
-  int rc = ladmm_create_case(ctx, d1, &cur_c);
+  // pass 1's dose rates stay on the device: every later pass gathers its kept
+  // rows there and uploads only its new low-dose rows
+  double *dose1 = nullptr;
+  int32_t *keep_d = nullptr;
+  int rc = create_case_impl(ctx, d1, &cur_c, nullptr, n_passes > 1 ? &dose1 : nullptr);
   if (rc) return rc;
+  auto free_dev = [&]() {
+    if (dose1) hipFree(dose1);
+    if (keep_d) hipFree(keep_d);
+    dose1 = nullptr;
+    keep_d = nullptr;
+  };
+  if (n_passes > 1 && !keep.empty()) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&keep_d, keep.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(keep_d, keep.data(), keep.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      ladmm_destroy_case(cur_c);
+      free_dev();
+      return fail(LADMM_E_DEVICE, std::string("passes: ") + hipGetErrorString(e));
+    }
+  }
   auto t1 = clk::now();
   rc = ladmm_batch_create(cur_c, k, w, nullptr, nullptr, opts, &cur_b);
   if (rc == LADMM_OK) rc = ladmm_batch_run(cur_b);
@@ -2126,21 +2160,30 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
       rc = fail(LADMM_E_INVALID, "passes: empty or too large pass");
       break;
     }
-    // every row is written below, so the buffer is not cleared first; the kept
-    // rows (7 GB at 180,000 x 4,800) are copied by several host threads
-    std::unique_ptr<double[]> dose2(new double[(size_t)N2 * n_t]);
+    // this pass's dose rates on the device: the kept rows gathered from pass 1's
+    // copy, then the new low-dose rows of each set uploaded behind them
     std::vector<int32_t> grp2(N2);
+    for (size_t i = 0; i < keep.size(); ++i) grp2[i] = d1->point_group[keep[i]];
+    double *dose2 = nullptr;
     {
       const size_t nk = keep.size();
-      const size_t nth = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
-      std::vector<std::thread> pool;
-      for (size_t t = 0; t < nth; ++t)
-        pool.emplace_back([&, t] {
-          for (size_t i = nk * t / nth; i < nk * (t + 1) / nth; ++i)
-            std::memcpy(&dose2[i * n_t], d1->dose + (size_t)keep[i] * n_t, n_t * sizeof(double));
-        });
-      for (std::thread &th : pool) th.join();
-      for (size_t i = 0; i < nk; ++i) grp2[i] = d1->point_group[keep[i]];
+      size_t n_new = (size_t)(N2 - (int64_t)nk);
+      std::vector<double> rows_new(n_new * n_t);
+      size_t r = 0;
+      for (int st = 0; st < n_sets; ++st)
+        for (int64_t i = 0; i < nP[st]; ++i, ++r)
+          std::memcpy(&rows_new[r * n_t], sets[st].phi_vox + (size_t)P[st][i] * n_t, n_t * sizeof(double));
+      hipError_t e = hipSetDevice(ctx->device);
+      if (e == hipSuccess) e = hipMalloc((void **)&dose2, (size_t)N2 * n_t * sizeof(double));
+      if (e == hipSuccess && nk > 0) e = gather_rows(nullptr, dose1, dose2, (int)nk, (size_t)n_t, 8, keep_d);
+      if (e == hipSuccess && n_new > 0)
+        e = hipMemcpy(dose2 + nk * n_t, rows_new.data(), n_new * n_t * sizeof(double), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess) {
+        if (dose2) hipFree(dose2);
+        rc = fail(LADMM_E_DEVICE, std::string("passes: ") + hipGetErrorString(e));
+        break;
+      }
     }
     const int W2 = (int)((N2 + 63) / 64);
     std::vector<uint64_t> mask2((size_t)k * W2, 0);
@@ -2148,11 +2191,7 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
     for (int st = 0; st < n_sets; ++st) {
       const ladmm_pass2_desc &p2 = sets[st];
       const size_t Wv = (size_t)((p2.n_vox + 63) / 64);
-      for (int64_t i = 0; i < nP[st]; ++i) {
-        std::memcpy(&dose2[(size_t)(at + i) * n_t], p2.phi_vox + (size_t)P[st][i] * n_t,
-                    n_t * sizeof(double));
-        grp2[at + i] = p2.ld_group;
-      }
+      for (int64_t i = 0; i < nP[st]; ++i) grp2[at + i] = p2.ld_group;
       for (int j = 0; j < k; ++j)
         for (int64_t i = 0; i < nP[st]; ++i)
           if ((masks[st][(size_t)j * Wv + (i >> 6)] >> (i & 63)) & 1ull) {
@@ -2163,9 +2202,10 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
     }
     ladmm_case_desc d2 = *d1;
     d2.n_points = (int32_t)N2;
-    d2.dose = dose2.get();
+    d2.dose = nullptr;
     d2.point_group = grp2.data();
-    rc = ladmm_create_case(ctx, &d2, &cur_c);
+    rc = create_case_impl(ctx, &d2, &cur_c, dose2, nullptr);
+    hipFree(dose2);
     if (rc) break;
     auto tc = clk::now();
     rc = ladmm_batch_create(cur_c, k, w, mask2.data(), nullptr, opts, &cur_b);
@@ -2178,6 +2218,7 @@ int ladmm_passes(ladmm_ctx *ctx, const ladmm_case_desc *d1, int32_t k, const lad
   }
   if (cur_b) ladmm_batch_destroy(cur_b);
   if (cur_c) ladmm_destroy_case(cur_c);
+  free_dev();
   if (rc) return rc;
   if (times_ms) std::memcpy(times_ms, tm.data(), tm.size() * sizeof(double));
   if (P_out) {
