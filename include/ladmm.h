@@ -400,7 +400,11 @@ typedef struct {
  *   P:         optional host output, capacity n_vox: the selected voxel indices.
  *   n_points2: optional host output: |P| (first), then the pass-2 point count.
  *   times_ms:  optional host output[5]: wall time of pass-1 setup, pass-1 solve,
- *              band + Algorithm 1, pass-2 setup, pass-2 solve. */
+ *              band + Algorithm 1, pass-2 setup, pass-2 solve.
+ * Device memory: pass 1's dose rates (FP64, n_points x n_t x 8 bytes) stay on
+ * the device for the whole call, beside the context's budget; the pass-2 block
+ * is gathered from them and only the selected rows of phi_vox are uploaded.
+ * LADMM_E_DEVICE when these allocations or copies fail. */
 int ladmm_two_pass(ladmm_ctx *ctx, const ladmm_case_desc *pass1, int32_t k,
                    const ladmm_weights *w, const ladmm_opts *opts, const ladmm_pass2_desc *p2,
                    ladmm_result *pass1_out, ladmm_result *out, int64_t *P, int64_t *n_points2,
