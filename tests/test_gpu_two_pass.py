@@ -103,6 +103,37 @@ def test_two_pass_c0_reduced_precision_matches_oracle(precision):
     assert np.all(rel < 1e-3), rel
 
 
+def test_two_pass_c0_no_new_low_dose_points():
+    """N_LD,j = 0 for every plan: Algorithm 1 selects nothing, so the second-pass
+    case is the pass-1 points outside the low-dose group, gathered on the device
+    with no new rows (Sec. 2.C), and every pass-2 plan is within 1e-3 of the
+    exact optimum of that LP."""
+    say("two-pass c0 f64, no new low-dose points")
+    case = cases.make_case(0)
+    w = cases.config_weights(0)
+    k = w.shape[0]
+    ld_group = [g.type for g in case.groups].index(cases.LD)
+    phi = case.kernel.dose_rate(case.ld_candidates)
+    d_ld, delta = 0.5 * case.prescription_mean, 0.1 * case.prescription_mean
+    opts = ladmm.Options(max_iter=20000, check_every=50, tol_gap=1e-4, tol_pri=1e-4,
+                         tol_dual=1e-4, tol_cert=9e-4, rho0=1000.0, w0_bot=cases.W0_BOT)
+    ctx = ladmm.Context(0)
+    r1, r2, P, n2, times = ladmm.two_pass(ctx, case, w, phi, d_ld, delta, np.zeros(k, np.int32),
+                                          12345, ld_group, "f64", opts)
+    keep = np.nonzero(case.group != ld_group)[0]
+    assert len(P) == 0 and n2 == len(keep)
+    case2 = case.with_points(keep)
+    mask2 = np.zeros((k, n2), bool)
+    lp2 = olp.assemble(case2, w, mask2)
+    Fstar = np.array([-solve_plan(lp2, j).objective for j in range(k)])
+    F2 = olp.planning_objective(case2, w, r2["t"].T, mask2)[0]
+    assert np.max(np.abs(F2 - r2["objective"]) / Fstar) < 1e-9
+    rel = np.abs(F2 - Fstar) / Fstar
+    say("pass-2 rel err", rel, "status", r2["plan_status"], "iters", r2["iters"])
+    assert np.all(r2["plan_status"] == ladmm.PLAN_CONVERGED), r2["plan_status"]
+    assert np.all(rel < 1e-3), rel
+
+
 def test_two_pass_two_low_dose_thresholds_c0():
     """Two low-dose groups (thresholds 0.5 and 0.25 of the prescription, App. A)
     replaced in one call: each set's point set is the oracle's band + Algorithm 1
