@@ -441,7 +441,7 @@ def sweep(dc, w, opts, label):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
     if args.workload == "uneven":
         return uneven(args)

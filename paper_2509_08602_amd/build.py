@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libladmm.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
 ARCH = "gfx950"
-# Packed FP32 instructions are kept out of the generated code (see DESIGN).
+# Packed FP32 instructions are kept out of the generated code: some of their forms have
+# given wrong results on gfx950 without an error, and plain FP32 code needs none.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-value", "-Wno-unused-result",
